@@ -1,0 +1,147 @@
+"""Seeded synthetic inputs for the shell runs (no spectral-difference arithmetic).
+
+This module only draws random numbers and evaluates closed-form initial data at
+positions it is given; it is shared by the product driver, the benchmark and
+the tests so that the oracle and the HIP library see identical inputs.
+
+* Background: the adiabatic polytrope in hydrostatic balance of the paper's
+  section "Initial Conditions" (profiles of p, rho, T in terms of the potential
+  Phi = -GM/r, with T_b fixed by the number of density scale heights N_rho so
+  that rho_t / rho_b = exp(-N_rho)).
+* Perturbations (synthetic, seeded): velocity 1e-4 * U(-1,1) per component per
+  point times sin(pi (r - r_b)/(r_t - r_b)); a dipole seed field
+  1e-3 (r_b/r)^3 (3 (z.r) r - z); psi = 0.
+* Run parameters: nondimensional units GM = R = 1, gamma = 5/3; kinematic
+  viscosity, thermal and magnetic diffusivities from seeded Prandtl and magnetic
+  Prandtl numbers in [0.5, 4].
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+GAMMA = 5.0 / 3.0
+
+
+@dataclasses.dataclass
+class Background:
+    """Polytrope of the section "Initial Conditions" in nondimensional units."""
+    N_rho: float
+    rb: float = 0.70
+    rt: float = 0.98
+    GM: float = 1.0
+    Rgas: float = 1.0
+    gamma: float = GAMMA
+    rho_b: float = 1.0
+
+    @property
+    def cp(self):
+        return self.gamma * self.Rgas / (self.gamma - 1.0)
+
+    @property
+    def T_b(self):
+        phi_b, phi_t = -self.GM / self.rb, -self.GM / self.rt
+        return (phi_t - phi_b) / (self.cp * (1.0 - np.exp(-(self.gamma - 1.0) * self.N_rho)))
+
+    @property
+    def p_b(self):
+        return self.rho_b * self.Rgas * self.T_b
+
+    def profile(self, r):
+        """(rho, p, T) at radius r."""
+        r = np.asarray(r, dtype=np.float64)
+        z = 1.0 - (-self.GM / r + self.GM / self.rb) / (self.cp * self.T_b)
+        g1 = self.gamma - 1.0
+        return (self.rho_b * z ** (1.0 / g1), self.p_b * z ** (self.gamma / g1), self.T_b * z)
+
+    @property
+    def T_t(self):
+        return float(self.profile(self.rt)[2])
+
+
+def radius(x: np.ndarray) -> np.ndarray:
+    """|x| over axis 1, squares summed in ascending order so that positions
+    related by a signed permutation of the axes get bit-identical radii."""
+    return np.sqrt(np.sort(x * x, axis=1).sum(axis=1))
+
+
+def shell_state(x_sp: np.ndarray, bg: Background, seed: int, u_amp=1e-4, b_amp=1e-3) -> np.ndarray:
+    """Conserved state Q [E][9][N^3] (rho, rho u, E, B, psi) at positions x_sp [E][3][N^3]."""
+    x = np.asarray(x_sp, dtype=np.float64)
+    E, _, n3 = x.shape
+    r = radius(x)
+    rho, p, _ = bg.profile(r)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = u_amp * rng.uniform(-1.0, 1.0, size=(E, 3, n3))
+    u *= np.sin(np.pi * (r - bg.rb) / (bg.rt - bg.rb))[:, None, :]
+    rhat = x / r[:, None, :]
+    cz = rhat[:, 2, :]
+    B = b_amp * (bg.rb / r)[:, None, :] ** 3 * (3.0 * cz[:, None, :] * rhat - np.array([0.0, 0.0, 1.0])[None, :, None])
+    Q = np.empty((E, 9, n3))
+    Q[:, 0] = rho
+    Q[:, 1:4] = rho[:, None, :] * u
+    Q[:, 4] = p / (bg.gamma - 1.0) + 0.5 * rho * (u * u).sum(axis=1) + 0.5 * (B * B).sum(axis=1)
+    Q[:, 5:8] = B
+    Q[:, 8] = 0.0
+    return Q
+
+
+def smooth_random_state(x_sp: np.ndarray, seed: int, gamma=GAMMA) -> np.ndarray:
+    """A smooth, far-from-equilibrium state (random low Fourier modes)."""
+    x = np.asarray(x_sp, dtype=np.float64)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    E, _, n3 = x.shape
+
+    def field(amp):
+        k = rng.integers(-2, 3, size=(3, 3)).astype(float)
+        ph = rng.uniform(0, 2 * np.pi, size=3)
+        a = rng.uniform(-1, 1, size=3)
+        s = np.zeros((E, n3))
+        for m in range(3):
+            s += a[m] * np.sin(np.pi * np.einsum("d,edq->eq", k[m], x) + ph[m])
+        return amp * s
+
+    rho = 1.0 + field(0.2)
+    u = np.stack([field(0.3) for _ in range(3)], axis=1)
+    p = 1.0 + field(0.2)
+    B = np.stack([field(0.4) for _ in range(3)], axis=1)
+    psi = field(0.05)
+    Q = np.empty((E, 9, n3))
+    Q[:, 0] = rho
+    Q[:, 1:4] = rho[:, None, :] * u
+    Q[:, 4] = p / (gamma - 1.0) + 0.5 * rho * (u * u).sum(axis=1) + 0.5 * (B * B).sum(axis=1) + 0.5 * psi * psi
+    Q[:, 5:8] = B
+    Q[:, 8] = psi
+    return Q
+
+
+def run_params(seed: int, bg: Background, nu=2.0e-5, Omega=0.12, q_inner=1.0e-4) -> dict:
+    """Physical parameters of one synthetic dynamo run (seeded Pr, Pm in [0.5, 4])."""
+    rng = np.random.Generator(np.random.PCG64(seed + 7919))
+    Pr, Pm = rng.uniform(0.5, 4.0, size=2)
+    return dict(gamma=bg.gamma, Rgas=bg.Rgas, GM=bg.GM, Omega=Omega, nu=nu, kappa=nu / Pr,
+                eta=nu / Pm, kr_scale=0.0, kr_c0=0.0, kr_c1=0.0, kr_c2=0.0, kr_omega_per_r=0.0,
+                powell=1, wall_kind=(0, 0), wall_mag=(0, 1), wall_th=(0, 1),
+                q_wall=(q_inner, 0.0), T_wall=(bg.T_b, bg.T_t))
+
+
+def glm_speed(Q: np.ndarray, gamma=GAMMA) -> float:
+    """c_h = max over points of |u| + sqrt(a^2 + b^2) (largest signal speed of Q)."""
+    rho = Q[:, 0]
+    u2 = (Q[:, 1:4] ** 2).sum(axis=1) / rho ** 2
+    b2 = (Q[:, 5:8] ** 2).sum(axis=1)
+    p = (gamma - 1.0) * (Q[:, 4] - 0.5 * rho * u2 - 0.5 * b2 - 0.5 * Q[:, 8] ** 2)
+    return float(np.max(np.sqrt(u2) + np.sqrt(gamma * p / rho + b2 / rho)))
+
+
+def time_step(Q: np.ndarray, S_sp: np.ndarray, detJ: np.ndarray, c_h: float, cfl: float,
+              gamma=GAMMA) -> float:
+    """dt = cfl / max over points of lambda * sum_d |S^d| / |J| (lambda incl. c_h)."""
+    rho = Q[:, 0]
+    u2 = (Q[:, 1:4] ** 2).sum(axis=1) / rho ** 2
+    b2 = (Q[:, 5:8] ** 2).sum(axis=1)
+    p = (gamma - 1.0) * (Q[:, 4] - 0.5 * rho * u2 - 0.5 * b2 - 0.5 * Q[:, 8] ** 2)
+    lam = np.maximum(np.sqrt(u2) + np.sqrt(gamma * p / rho + b2 / rho), c_h)
+    inv_h = np.sqrt((S_sp ** 2).sum(axis=2)).sum(axis=1) / np.abs(detJ)
+    return float(cfl / np.max(lam * inv_h))
