@@ -1,0 +1,209 @@
+"""Throughput benchmark of the spectral-difference GLM-MHD hot path on one MI355X.
+
+One benchmark "step" is one full SSPRK(5,3) time step = five fused RK stages,
+each a complete residual evaluation (traces, BR1 common solution, gradients,
+fluxes, Riemann fluxes, divergence, sources) plus the Shu-Osher update, over
+the whole synthetic shell.  Inputs (state, registers, metrics) are resident in
+HBM before the timed region.
+
+Workload (default): the 55,296-element cubed-sphere shell (6 x 24 x 24 x 16,
+degree p = 5, 11.9M solution points x 9 FP64 variables), polytropic background
+with N_rho = 5 plus seeded perturbations, rotation, viscosity/conduction/
+resistivity, Powell and GLM terms, conducting heat-flux inner wall and
+radial-field fixed-temperature outer wall.
+
+Output: one JSON line (metric: DOF x RK-stage updates per second, FP64) with
+the FP32-mixed figure beside it, the roofline of the dominant kernel (from HIP
+events recorded around each launch in the timed region), and the FP64 CPU
+oracle timed on this host on a bounded sample (one SSPRK step of the same
+workload).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+CONFIGS = {  # name: (Nz, Nr, p, N_rho, seed)
+    "shell_55296_p5": (24, 16, 5, 5.0, 2),
+    "shell_6912_p5": (12, 8, 5, 3.0, 1),
+    "shell_48_p5": (2, 2, 5, 3.0, 0),
+}
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def kernel_bytes(kind, N, E, rs, n_in_avg):
+    """Algorithmic bytes one launch of a kernel moves (each input read once,
+    each output written once; rs = bytes of the residual arithmetic type)."""
+    N2, N3, NF = N * N, N ** 3, (N + 1) * N * N
+    if kind == "volume":
+        per = 8 * (9 * N3 + 9 * NF + N3 + 3 * N3 + 6 * 3 * N2) + 24 + rs * (6 * 9 * N2 + 9 * N3 + 6 * 7 * N2)
+    elif kind == "finish_stage":
+        per = 8 * (N3 + n_in_avg * 9 * N3 + 9 * N3) + 24 + rs * (9 * N3 + 6 * 7 * N2 + 6 * 9 * N2)
+    elif kind == "traces":
+        per = 8 * 9 * N3 + rs * 6 * 9 * N2
+    else:
+        return None
+    return per * E
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("sdm_kernels.hip", "sdm_physics.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2502_17805_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, config, arith):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        ent = d.get(f"{kernel}/{config}/{'fp64' if arith == 0 else 'mixed'}")
+        if not ent or ent.get("source_hash") != kernel_source_hash():
+            return None
+        return float(ent["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def run_gpu(sd, inp, cfg_name, arith, steps, warmup, mesh, Q, pr, dt):
+    import torch
+    s = sd.Solver(mesh, arith=arith)
+    prm = sd.make_params(**pr)
+    s.set_state(torch.from_numpy(Q))
+    for _ in range(warmup):
+        s.step(prm, dt)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.profile(True)
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.step(prm, dt)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    prof = s.profile_read()
+    s.profile(False)
+    d = s.diagnostics(prm)
+    return ms, wall, prof, d
+
+
+def cpu_baseline(cfg, Q_fn, pr, dt):
+    from oracle import oracle as o
+    Nz, Nr, p, _, _ = cfg
+    m = o.Mesh.shell(p + 1, Nz, Nr)
+    Q = Q_fn(m.get("x_sp"))
+    prm = o.make_params(**pr)
+    t0 = time.perf_counter()
+    m.step(prm, Q, dt)
+    t = time.perf_counter() - t0
+    dof = m.E * (p + 1) ** 3
+    return {"value": dof * 5 / t, "unit": "DOF*RK-stage updates/s", "cores": o.threads(), "kind": "oracle",
+            "sample": f"one SSPRK(5,3) step (5 stages) of the same {m.E}-element p={p} shell, "
+                      f"FP64 C oracle, OpenMP over elements, {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="shell_55296_p5", choices=sorted(CONFIGS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cfl", type=float, default=0.1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): sharding the shell "
+              "across GPUs is not built in this library", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2502_17805_amd import inputs as inp
+    from paper_2502_17805_amd import sdmhd as sd
+
+    cfg = CONFIGS[args.config]
+    Nz, Nr, p, N_rho, seed = cfg
+    N = p + 1
+    t0 = time.perf_counter()
+    mesh = sd.shell(Nz, Nr, p)
+    t_mesh = time.perf_counter() - t0
+    bg = inp.Background(N_rho)
+    Q = inp.shell_state(mesh.x_sp, bg, seed)
+    pr = inp.run_params(seed, bg)
+    ch = inp.glm_speed(Q)
+    pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
+    dt = inp.time_step(Q, mesh.S_sp, mesh.detJ, ch, args.cfl)
+    dof = mesh.E * N ** 3
+    print(f"# mesh {args.config}: E={mesh.E} DOF={dof} host build {t_mesh:.1f}s dt={dt:.3e}", file=sys.stderr,
+          flush=True)
+
+    res = {}
+    for arith in ((0,) if args.no_mixed else (0, 1)):
+        ms, wall, prof, d = run_gpu(sd, inp, args.config, arith, args.steps, args.warmup, mesh, Q, pr, dt)
+        res[arith] = (ms, wall, prof, d)
+        print(f"# arith={arith}: {ms / args.steps:.3f} ms/step; kernels {prof}; KE={d[3]:.3e} "
+              f"nan={d[8]}", file=sys.stderr, flush=True)
+
+    ms, wall, prof, diag = res[0]
+    stages = 5 * args.steps
+    value = dof * stages / (ms * 1e-3)
+    # roofline of the dominant kernel (largest summed time)
+    dom = max(prof, key=lambda k: prof[k][0])
+    avg_ms = prof[dom][0] / prof[dom][1]
+    n_in_avg = (1 + 2 + 3 + 4) / 5.0 + 0.0  # extra register reads per stage besides the current state
+    bytes_launch = kernel_bytes(dom, N, mesh.E, 8, n_in_avg)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if bytes_launch else None
+    traffic = measured_traffic(dom, args.config, 0)
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
+            "kernel": f"k_volume<N={N},double>" if dom == "volume" else dom,
+            "avg_launch_ms": avg_ms}
+    out = {
+        "metric": "SD-MHD DOF*RK-stage updates/s (FP64)",
+        "value": value,
+        "unit": "DOF*RK-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"cubed-sphere shell 6x{Nz}x{Nz}x{Nr} = {mesh.E} elements, p={p}, "
+                               f"{dof} solution points x 9 vars, N_rho={N_rho:g}, SSPRK(5,3) step = 5 stages",
+                   "elements": mesh.E, "p": p, "dof": dof, "stages_per_step": 5, "parallelism": "single GPU"},
+        "roofline": roof,
+        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+    }
+    if 1 in res:
+        ms1, _, prof1, d1 = res[1]
+        out["mixed_fp32"] = {"value": dof * stages / (ms1 * 1e-3), "ms_per_step": ms1 / args.steps,
+                             "kernels_ms_per_step": {k: v[0] / args.steps for k, v in prof1.items()},
+                             "speedup_vs_fp64": ms / ms1}
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(cfg, lambda x: inp.shell_state(x, bg, seed), pr, dt)
+        except Exception as ex:  # report, do not hide
+            out["cpu_baseline"] = {"value": None, "error": repr(ex)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * sdmhd.h -- C ABI of the MI355X (gfx950) spectral-difference GLM-MHD library.
+ *
+ * The library advances the compressible, viscous, resistive MHD equations
+ * with a generalised-Lagrange-multiplier cleaning field psi (9 conserved
+ * variables Q = rho, rho u, E, B, psi; paper arXiv 2502.17805, Sec. "MHD
+ * Governing Equations", Eq. "General Form1") on hexahedral elements of a
+ * mapped cubed-sphere shell (Sec. "Meshing") with the spectral-difference
+ * method of Sec. "Spectral Difference Method" and the SSPRK(5,3) integrator
+ * named there.  Device work is hand-written HIP; every pointer marked
+ * "device" must be device memory of the context's GPU, allocated and owned
+ * by the caller (the library never frees it and allocates no device memory
+ * except its static constant tables).  Calls that take a stream only enqueue
+ * work on it; results are valid after the stream is synchronised.
+ *
+ * Layouts (all row-major, last index fastest):
+ *   N      = p + 1 solution points per direction; N3 = N^3; NF = (N+1) N^2
+ *   point  (a, b, c) -> a + N b + N^2 c   (a along xi, b along eta, c along zeta)
+ *   Q, R   [E][9][N3]   variable order rho, rho u_x, rho u_y, rho u_z, E,
+ *                       B_x, B_y, B_z, psi (FP64)
+ *   x_sp   [E][3][N3]   physical solution-point coordinates (FP64)
+ *   detJ   [E][N3]      Jacobian determinant at the solution points (FP64)
+ *   S_fp   [E][3 d][3 x][NF]  metric vector S^d = |J| grad(xi_d) at the
+ *                       family-d flux points; family d stores its flux-point
+ *                       index along axis d (d = 0: f + (N+1)(b + N c);
+ *                       d = 1: a + N (f + (N+1) c); d = 2: a + N (b + N f))
+ *   nbr    [E][6]       int32 per element face (0/1: xi = 0/1, 2/3: eta,
+ *                       4/5: zeta).  Interior: (e' << 6) | (f' << 3) | o,
+ *                       neighbour element e', its face f', orientation o.
+ *                       Boundary: -(1 + group + 4 * bface), group 0 = zeta=0
+ *                       wall (inner sphere), 1 = zeta=1 wall (outer sphere),
+ *                       2 = other (always Dirichlet); bface numbers the
+ *                       boundary faces in (element, face) order.
+ *   face-local point (a, b): the two axes other than the face normal, in
+ *   increasing axis order; orientation o = 4 swap + 2 flip_b + flip_a maps
+ *   it to the neighbour's point: (p, q) = swap ? (b, a) : (a, b);
+ *   a' = flip_a ? N-1-p : p; b' = flip_b ? N-1-q : q.
+ *   ghost  [n_bfaces][9][N^2]  outside state on Dirichlet faces (device).
+ *
+ * Errors: every call returns an sdm_status; nothing is thrown across the
+ * ABI.  SDM_EINVAL: bad sizes, NULL pointers, unsupported p; SDM_EHIP: a HIP
+ * runtime error (text in sdm_last_error()).  NaN/Inf in the state is not an
+ * API error: sdm_diagnostics reports it.
+ */
+#ifndef SDMHD_H
+#define SDMHD_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SDM_OK = 0,
+  SDM_EINVAL = -1,
+  SDM_ENOMEM = -2,
+  SDM_EHIP = -3,
+  SDM_ESTATE = -4,
+  SDM_EUNSUPPORTED = -5
+} sdm_status;
+
+typedef struct sdm_ctx sdm_ctx;
+
+/* Message for the last non-OK status returned on this thread. */
+const char* sdm_last_error(void);
+
+/* Library version string. */
+const char* sdm_version(void);
+
+/* ---------------- host-side mesh construction (no GPU needed) ---------- */
+
+/* Element and boundary-face counts of the cubed-sphere shell with Nz x Nz
+ * elements per cube face and Nr radial layers (Sec. "Meshing":
+ * N_cells = 6 N_r N_z^2).  n_bfaces = 12 Nz^2. */
+sdm_status sdm_shell_sizes(int Nz, int Nr, int64_t* n_elem, int64_t* n_bfaces);
+
+/* Build the shell of degree p between radii rb < rt into caller HOST
+ * buffers sized from sdm_shell_sizes (layouts above).  S_sp ([E][3][3][N3],
+ * the metric vectors at the solution points) may be NULL.  Element index
+ * e = ((P Nr + k) Nz + j) Nz + i for cube patch P (+x,+y,-x,-y,+z,-z),
+ * radial layer k (inner to outer), and equiangular indices (i, j).
+ * The element map is the degree-N isoparametric interpolant of the exact
+ * shell through the (N+1)^3 flux-point nodes; metrics use the invariant
+ * curl form (paper, Sec. "Spectral Difference Method": transfinite map P,
+ * Jacobi matrix J, transformed system Eq. "G.E. comp").  Uses all host
+ * threads (OpenMP). */
+sdm_status sdm_shell_build(int Nz, int Nr, int p, double rb, double rt, double* x_sp,
+                           double* detJ, double* S_fp, double* S_sp, int32_t* nbr);
+
+/* The same for an nx x ny x nz box [0,Lx]x[0,Ly]x[0,Lz] (element index
+ * e = (k ny + j) nx + i), periodic in direction d if bit d of `periodic` is
+ * set (needs >= 3 elements there), node positions displaced by the smooth
+ * periodic warp  w sin(2 pi x/Lx) sin(2 pi y/Ly) sin(2 pi z/Lz) (L_d each).
+ * Boundary faces at z = 0 / z = Lz are groups 0 / 1, others group 2.
+ * n_bfaces is returned through *n_bfaces (may be NULL). */
+sdm_status sdm_box_sizes(int nx, int ny, int nz, int periodic, int64_t* n_elem,
+                         int64_t* n_bfaces);
+sdm_status sdm_box_build(int nx, int ny, int nz, double Lx, double Ly, double Lz,
+                         int periodic, double warp, int p, double* x_sp, double* detJ,
+                         double* S_fp, double* S_sp, int32_t* nbr);
+
+/* 1-D tables of the method for N = p+1 (host): solution points xs[N],
+ * flux points xf[N+1], interpolation I[(N+1)][N] (SP basis at FPs),
+ * derivative D[N][N+1] (FP basis derivative at SPs), weights W[N]. */
+sdm_status sdm_tables(int p, double* xs, double* xf, double* I, double* D, double* W);
+
+/* ---------------- device context ------------------------------------- */
+
+/* arith: 0 = FP64 throughout; 1 = mixed (FP32 residual arithmetic, FP64
+ * state, RK accumulation, metrics and diagnostics).  p in 1..6 (the FP64
+ * volume kernel of p = 7 would exceed the 160 KB of LDS). */
+sdm_status sdm_create(int device, int p, int arith, sdm_ctx** out);
+sdm_status sdm_destroy(sdm_ctx* ctx);
+
+/* Borrowed DEVICE arrays of one mesh (layouts above); they must outlive
+ * every call that uses them. */
+typedef struct {
+  int64_t n_elem;
+  int64_t n_bfaces;
+  const double* x_sp;
+  const double* detJ;
+  const double* S_fp;
+  const int32_t* nbr;
+} sdm_mesh;
+sdm_status sdm_mesh_bind(sdm_ctx* ctx, const sdm_mesh* mesh);
+
+/* Physical and boundary parameters (nondimensional).
+ *  mu = rho nu, lambda = -2/3 mu (Eq. "ssTensor"); heat flux
+ *  q = -kappa rho T grad S - kappa_r rho c_p grad T (Eq. "qFlux") with
+ *  kappa_r(r) = kr_scale (kr_c0 + kr_c1 w + kr_c2 w^2), w = r kr_omega_per_r;
+ *  GLM speed c_h and damping a (source -a psi); powell != 0 enables the
+ *  div-B source terms of Eq. "M".  Walls (group 0 inner, 1 outer):
+ *  wall_kind 0 = physical wall, 1 = Dirichlet ghost buffer; wall_mag 0 =
+ *  perfectly conducting, 1 = perfectly radial field; wall_th 0 = prescribed
+ *  outward-radial heat-flux density q_wall, 1 = fixed temperature T_wall
+ *  (Sec. "Problem Formulation and Boundary Conditions"). */
+typedef struct {
+  double gamma, Rgas, GM, Omega, nu, kappa, eta;
+  double kr_scale, kr_c0, kr_c1, kr_c2, kr_omega_per_r;
+  double c_h, glm_a;
+  int32_t powell;
+  int32_t wall_kind[2];
+  int32_t wall_mag[2];
+  int32_t wall_th[2];
+  double q_wall[2];
+  double T_wall[2];
+  const double* ghost; /* device [n_bfaces][9][N^2] or NULL */
+} sdm_params;
+
+/* Bytes of scratch (face traces, partial residual) one call needs; the
+ * caller allocates it (device, 256-byte aligned) and passes it as `ws`. */
+sdm_status sdm_workspace_size(const sdm_ctx* ctx, size_t* bytes);
+
+/* R = dQ/dt at the solution points (device Q, R, layout [E][9][N3]). */
+sdm_status sdm_residual(sdm_ctx* ctx, const sdm_params* prm, const double* Q, double* R,
+                        void* ws, void* stream);
+
+/* One explicit Runge-Kutta stage in Shu-Osher form, fused into the last
+ * pass of the residual:
+ *   regs[out] = sum_k alpha[k] regs[in[k]] + beta dt R(regs[cur])
+ * regs: n_regs device state buffers ([E][9][N3] FP64); out may equal cur or
+ * an input (each element reads before it writes).  The SSPRK(5,3) step of
+ * the paper is five such stages.  Every stage leaves the face traces of
+ * regs[out] in `ws`; traces_valid != 0 tells the next call that `ws` holds
+ * the traces of its regs[cur] (it then skips recomputing them); pass 0
+ * whenever the state was changed by anything else. */
+typedef struct {
+  int32_t n_in;
+  int32_t in_idx[4];
+  double alpha[4];
+  int32_t cur;
+  int32_t out;
+  double beta;
+  int32_t traces_valid;
+} sdm_stage;
+sdm_status sdm_rk_stage(sdm_ctx* ctx, const sdm_params* prm, double* const* regs, int n_regs,
+                        const sdm_stage* stage, double dt, void* ws, void* stream);
+
+/* Diagnostics of state Q into DEVICE out[16] (FP64): volume, mass, total
+ * energy, volume-averaged KE = (1/V) int rho|u|^2/2, E_B = (1/V) int
+ * |B|^2/2 (Sec. "Results"), max|div B|, L2 norm of div B, max|psi|, NaN/Inf
+ * flag (1.0 if any), zeros after.  Deterministic (fixed reduction order). */
+sdm_status sdm_diagnostics(sdm_ctx* ctx, const sdm_params* prm, const double* Q, double* out,
+                           void* ws, void* stream);
+
+/* Per-kernel timing for benchmarks.  While enabled, every launch the
+ * context makes is bracketed by two HIP events recorded on the call's
+ * stream.  sdm_profile_read waits for them, then returns per kernel kind
+ * (0 trace pass, 1 volume pass, 2 diagnostics volume pass, 3 residual
+ * finish, 4 stage finish) the summed milliseconds ms[8] and launch counts
+ * count[8], and forgets the recorded launches.  Enabling again clears. */
+sdm_status sdm_profile_enable(sdm_ctx* ctx, int enable);
+sdm_status sdm_profile_read(sdm_ctx* ctx, double* ms, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,40 @@
+"""Build the gfx950 library in-tree: paper_2502_17805_amd/libsdmhd.so.
+
+The HIP kernels and the C ABI are compiled with hipcc for gfx950 (packed FP32
+instructions disabled); the host mesh/metric code is compiled with g++ and
+OpenMP and linked in.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libsdmhd.so")
+ARCH = os.environ.get("SDM_OFFLOAD_ARCH", "gfx950")
+
+
+def _run(cmd):
+    print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
+def build(verbose=True) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    host_o = os.path.join(BUILD, "sdm_host.o")
+    kern_o = os.path.join(BUILD, "sdm_kernels.o")
+    _run(["g++", "-std=c++17", "-O2", "-fPIC", "-fopenmp", "-Wall", "-c",
+          os.path.join(CSRC, "sdm_host.cpp"), "-o", host_o])
+    _run(["hipcc", f"--offload-arch={ARCH}", "-std=c++17", "-O3", "-fPIC",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-c", os.path.join(CSRC, "sdm_kernels.hip"), "-o", kern_o])
+    tmp = LIB + ".tmp"
+    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, kern_o, host_o, "-lgomp"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()
+    sys.exit(0)

@@ -1,0 +1,447 @@
+// sdm_host.cpp -- host-side setup of the spectral-difference library:
+// 1-D tables, cubed-sphere / box meshes, face connectivity and the metric
+// terms of the transformed equations (paper arXiv 2502.17805, Sec. "Meshing"
+// and Sec. "Spectral Difference Method").  Runs once per mesh, on the CPU.
+#include "sdm_host.hpp"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <unordered_map>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace sdm {
+
+using ld = long double;
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// 1-D tables
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Roots of the Legendre polynomial P_m on (-1, 1), ascending.  Newton on the
+// three-term recurrence, started from the asymptotic estimate of each root.
+std::vector<ld> legendre_zeros(int m) {
+  std::vector<ld> z(m);
+  const ld pi = 3.141592653589793238462643383279502884L;
+  for (int k = 1; k <= m; ++k) {
+    ld x = -std::cos(pi * (k - 0.25L) / (m + 0.5L));  // k-th smallest
+    for (int it = 0; it < 60; ++it) {
+      ld pm1 = 1, p = x;  // P_0, P_1
+      for (int n = 2; n <= m; ++n) {
+        ld pn = ((2 * n - 1) * x * p - (n - 1) * pm1) / n;
+        pm1 = p;
+        p = pn;
+      }
+      if (m == 1) { p = x; pm1 = 1; }
+      ld dp = m * (x * p - pm1) / (x * x - 1);
+      ld step = p / dp;
+      x -= step;
+      if (std::fabs(step) < 1e-21L) break;
+    }
+    z[k - 1] = x;
+  }
+  return z;
+}
+
+// Lagrange basis j over `nodes` and its derivative at x (x not a node for
+// the derivative form used here: l'_j(x) = l_j(x) sum_{k != j} 1/(x - x_k)).
+ld lagrange(const std::vector<ld>& nodes, int j, ld x) {
+  ld v = 1;
+  for (size_t k = 0; k < nodes.size(); ++k)
+    if ((int)k != j) v *= (x - nodes[k]) / (nodes[j] - nodes[k]);
+  return v;
+}
+ld lagrange_deriv(const std::vector<ld>& nodes, int j, ld x) {
+  for (size_t k = 0; k < nodes.size(); ++k)
+    if (std::fabs(x - nodes[k]) < 1e-30L) {
+      // x is node k: differentiation-matrix entry
+      if ((int)k != j) {
+        ld wj = 1, wk = 1;
+        for (size_t m = 0; m < nodes.size(); ++m) {
+          if ((int)m != j) wj *= nodes[j] - nodes[m];
+          if (m != k) wk *= nodes[k] - nodes[m];
+        }
+        return (wk / wj) / (nodes[k] - nodes[j]);
+      }
+      ld s = 0;
+      for (size_t m = 0; m < nodes.size(); ++m)
+        if ((int)m != j) s += 1 / (nodes[j] - nodes[m]);
+      return s;
+    }
+  ld s = 0;
+  for (size_t k = 0; k < nodes.size(); ++k)
+    if ((int)k != j) s += 1 / (x - nodes[k]);
+  return lagrange(nodes, j, x) * s;
+}
+
+}  // namespace
+
+Tables1D make_tables(int N) {
+  Tables1D t;
+  t.N = N;
+  const ld pi = 3.141592653589793238462643383279502884L;
+  std::vector<ld> xs(N), xf(N + 1);
+  for (int n = 1; n <= N; ++n) xs[n - 1] = (1 - std::cos((2 * n - 1) * pi / (2 * N))) / 2;
+  std::vector<ld> z = legendre_zeros(N - 1);
+  xf[0] = 0;
+  for (int k = 0; k < N - 1; ++k) xf[k + 1] = (1 + z[k]) / 2;
+  xf[N] = 1;
+  t.xs.assign(xs.begin(), xs.end());
+  t.xf.assign(xf.begin(), xf.end());
+  t.I.resize((N + 1) * N);
+  t.D.resize(N * (N + 1));
+  t.L.resize(N * (N + 1));
+  t.Dff.resize((N + 1) * (N + 1));
+  t.DI.resize(N * N);
+  for (int f = 0; f <= N; ++f)
+    for (int i = 0; i < N; ++i) t.I[f * N + i] = (double)lagrange(xs, i, xf[f]);
+  for (int i = 0; i < N; ++i)
+    for (int f = 0; f <= N; ++f) {
+      t.D[i * (N + 1) + f] = (double)lagrange_deriv(xf, f, xs[i]);
+      t.L[i * (N + 1) + f] = (double)lagrange(xf, f, xs[i]);
+    }
+  for (int g = 0; g <= N; ++g)
+    for (int f = 0; f <= N; ++f) t.Dff[g * (N + 1) + f] = (double)lagrange_deriv(xf, f, xf[g]);
+  // derivative of the solution polynomial itself at the SPs: (D I)_ij = h_j'(xs_i)
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) t.DI[i * N + j] = (double)lagrange_deriv(xs, j, xs[i]);
+  // weights W_i = integral of h_i over [0,1]: solve the moment equations
+  // sum_i W_i xs_i^k = 1/(k+1), k < N, by Gaussian elimination (long double)
+  std::vector<ld> A(N * (N + 1));
+  for (int k = 0; k < N; ++k) {
+    for (int i = 0; i < N; ++i) A[k * (N + 1) + i] = std::pow(xs[i], (ld)k);
+    A[k * (N + 1) + N] = 1.0L / (k + 1);
+  }
+  for (int c = 0; c < N; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < N; ++r)
+      if (std::fabs(A[r * (N + 1) + c]) > std::fabs(A[piv * (N + 1) + c])) piv = r;
+    for (int q = 0; q <= N; ++q) std::swap(A[c * (N + 1) + q], A[piv * (N + 1) + q]);
+    for (int r = 0; r < N; ++r) {
+      if (r == c) continue;
+      ld fct = A[r * (N + 1) + c] / A[c * (N + 1) + c];
+      for (int q = c; q <= N; ++q) A[r * (N + 1) + q] -= fct * A[c * (N + 1) + q];
+    }
+  }
+  t.W.resize(N);
+  for (int i = 0; i < N; ++i) t.W[i] = (double)(A[i * (N + 1) + N] / A[i * (N + 1) + i]);
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry of one element
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Small dense operator applied along one axis of an (n0, n1, n2) block.
+struct Block3 {
+  int n[3];
+  std::vector<double> v;
+  Block3(int a, int b, int c) : n{a, b, c}, v((size_t)a * b * c, 0.0) {}
+  double& at(int i, int j, int k) { return v[i + n[0] * (j + n[1] * k)]; }
+  double at(int i, int j, int k) const { return v[i + n[0] * (j + n[1] * k)]; }
+};
+
+// out = M applied along `axis` (M has `rows` rows and n[axis] columns)
+Block3 along(const Block3& in, int axis, const double* M, int rows) {
+  int m[3] = {in.n[0], in.n[1], in.n[2]};
+  m[axis] = rows;
+  Block3 out(m[0], m[1], m[2]);
+  const int cols = in.n[axis];
+  for (int k = 0; k < m[2]; ++k)
+    for (int j = 0; j < m[1]; ++j)
+      for (int i = 0; i < m[0]; ++i) {
+        int idx[3] = {i, j, k};
+        const int r = idx[axis];
+        double acc = 0.0;
+        for (int c = 0; c < cols; ++c) {
+          idx[axis] = c;
+          acc += M[r * cols + c] * in.at(idx[0], idx[1], idx[2]);
+        }
+        out.at(i, j, k) = acc;
+      }
+  return out;
+}
+
+enum Op { KEEP, VAL, DER };  // keep node index / value at SPs / derivative at SPs
+
+Block3 sample(const Tables1D& t, const Block3& nodes, Op o0, Op o1, Op o2) {
+  Block3 cur = nodes;
+  const Op ops[3] = {o0, o1, o2};
+  for (int ax = 0; ax < 3; ++ax) {
+    if (ops[ax] == KEEP) continue;
+    cur = along(cur, ax, ops[ax] == VAL ? t.L.data() : t.D.data(), t.N);
+  }
+  return cur;
+}
+
+// Metric data of one element from the map nodes X[c] (c = x, y, z) on the
+// (N+1)^3 flux-point tensor grid.
+void element_geometry(const Tables1D& t, const Block3 X[3], double* x_sp, double* detJ,
+                      double* S_fp, double* S_sp) {
+  const int N = t.N, NP = N + 1, N3 = N * N * N, NF = NP * N * N;
+  // derivatives of the map at the nodes
+  Block3 dX[3][3] = {{X[0], X[0], X[0]}, {X[0], X[0], X[0]}, {X[0], X[0], X[0]}};  // [axis][comp]
+  for (int ax = 0; ax < 3; ++ax)
+    for (int c = 0; c < 3; ++c) dX[ax][c] = along(X[c], ax, t.Dff.data(), NP);
+  // invariant curl form: S^i_n = d_k W_j - d_j W_k, (i,j,k) cyclic, with
+  // W_a = (X_l dX_m/dxi_a - X_m dX_l/dxi_a)/2, (n,m,l) cyclic
+  for (int n = 0; n < 3; ++n) {
+    const int mm = (n + 1) % 3, l = (n + 2) % 3;
+    Block3 W[3] = {X[0], X[0], X[0]};
+    for (int a = 0; a < 3; ++a)
+      for (size_t q = 0; q < W[a].v.size(); ++q)
+        W[a].v[q] = 0.5 * (X[l].v[q] * dX[a][mm].v[q] - X[mm].v[q] * dX[a][l].v[q]);
+    for (int i = 0; i < 3; ++i) {
+      const int j = (i + 1) % 3, k = (i + 2) % 3;
+      Op pa[3] = {VAL, VAL, VAL}, pb[3] = {VAL, VAL, VAL};
+      pa[i] = pb[i] = KEEP;  // family i keeps its flux-point index
+      pa[k] = DER;           // d_k W_j
+      pb[j] = DER;           // d_j W_k
+      Block3 A = sample(t, W[j], pa[0], pa[1], pa[2]);
+      Block3 B = sample(t, W[k], pb[0], pb[1], pb[2]);
+      double* out = S_fp + (i * 3 + n) * NF;
+      for (int q = 0; q < NF; ++q) out[q] = A.v[q] - B.v[q];
+      if (S_sp) {
+        pa[i] = pb[i] = VAL;
+        Block3 As = sample(t, W[j], pa[0], pa[1], pa[2]);
+        Block3 Bs = sample(t, W[k], pb[0], pb[1], pb[2]);
+        double* os = S_sp + (i * 3 + n) * N3;
+        for (int q = 0; q < N3; ++q) os[q] = As.v[q] - Bs.v[q];
+      }
+    }
+  }
+  // positions and Jacobian determinant at the solution points
+  Block3 J[3][3] = {{X[0], X[0], X[0]}, {X[0], X[0], X[0]}, {X[0], X[0], X[0]}};  // J[c][axis]
+  for (int c = 0; c < 3; ++c) {
+    Block3 p = sample(t, X[c], VAL, VAL, VAL);
+    std::memcpy(x_sp + c * N3, p.v.data(), sizeof(double) * N3);
+    J[c][0] = sample(t, X[c], DER, VAL, VAL);
+    J[c][1] = sample(t, X[c], VAL, DER, VAL);
+    J[c][2] = sample(t, X[c], VAL, VAL, DER);
+  }
+  for (int q = 0; q < N3; ++q) {
+    const double a = J[0][0].v[q], b = J[0][1].v[q], c = J[0][2].v[q];
+    const double d = J[1][0].v[q], e = J[1][1].v[q], f = J[1][2].v[q];
+    const double g = J[2][0].v[q], h = J[2][1].v[q], k = J[2][2].v[q];
+    detJ[q] = a * (e * k - f * h) - b * (d * k - f * g) + c * (d * h - e * g);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Connectivity from integer corner keys
+// ---------------------------------------------------------------------------
+
+using Key = std::array<int32_t, 4>;
+struct FaceKey {
+  std::array<Key, 4> c;  // sorted corner keys
+  bool operator==(const FaceKey& o) const { return c == o.c; }
+};
+struct FaceKeyHash {
+  size_t operator()(const FaceKey& k) const {
+    size_t h = 1469598103934665603ull;
+    for (const Key& q : k.c)
+      for (int32_t v : q) h = (h ^ (uint32_t)v) * 1099511628211ull;
+    return h;
+  }
+};
+
+// element corner (bit 0: xi, bit 1: eta, bit 2: zeta) at face-local corner (a,b)
+int corner_of(int face, int a, int b) {
+  const int ax = face >> 1, side = face & 1;
+  int bits[3];
+  bits[ax] = side;
+  const int o1 = ax == 0 ? 1 : 0, o2 = ax == 2 ? 1 : 2;
+  bits[o1] = a;
+  bits[o2] = b;
+  return bits[0] | (bits[1] << 1) | (bits[2] << 2);
+}
+
+void map_point(int o, int n, int a, int b, int& a2, int& b2) {
+  int p = a, q = b;
+  if (o & 4) std::swap(p, q);
+  a2 = (o & 1) ? n - 1 - p : p;
+  b2 = (o & 2) ? n - 1 - q : q;
+}
+
+// keys[e][8] -> nbr[e][6]; returns false on a non-manifold key set
+bool connect(int64_t E, const std::vector<Key>& keys, int32_t* nbr) {
+  std::unordered_map<FaceKey, int64_t, FaceKeyHash> open;
+  open.reserve((size_t)E * 4);
+  std::vector<int32_t> out((size_t)E * 6, INT32_MIN);
+  auto face_keys = [&](int64_t e, int f) {
+    FaceKey k;
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) k.c[a + 2 * b] = keys[e * 8 + corner_of(f, a, b)];
+    std::sort(k.c.begin(), k.c.end());
+    return k;
+  };
+  for (int64_t e = 0; e < E; ++e)
+    for (int f = 0; f < 6; ++f) {
+      FaceKey k = face_keys(e, f);
+      auto it = open.find(k);
+      if (it == open.end()) {
+        open.emplace(k, e * 6 + f);
+        continue;
+      }
+      const int64_t e2 = it->second / 6;
+      const int f2 = (int)(it->second % 6);
+      open.erase(it);
+      // orientation from (e,f) to (e2,f2) and back, matched on corner keys
+      int o12 = -1, o21 = -1;
+      for (int o = 0; o < 8; ++o) {
+        bool fw = true, bw = true;
+        for (int b = 0; b < 2; ++b)
+          for (int a = 0; a < 2; ++a) {
+            int a2, b2;
+            map_point(o, 2, a, b, a2, b2);
+            fw = fw && keys[e * 8 + corner_of(f, a, b)] == keys[e2 * 8 + corner_of(f2, a2, b2)];
+            bw = bw && keys[e2 * 8 + corner_of(f2, a, b)] == keys[e * 8 + corner_of(f, a2, b2)];
+          }
+        if (fw && o12 < 0) o12 = o;
+        if (bw && o21 < 0) o21 = o;
+      }
+      if (o12 < 0 || o21 < 0 || out[e * 6 + f] != INT32_MIN || out[e2 * 6 + f2] != INT32_MIN)
+        return false;
+      out[e * 6 + f] = (int32_t)((e2 << 6) | (f2 << 3) | o12);
+      out[e2 * 6 + f2] = (int32_t)((e << 6) | (f << 3) | o21);
+    }
+  int64_t nb = 0;
+  for (int64_t e = 0; e < E; ++e)
+    for (int f = 0; f < 6; ++f)
+      if (out[e * 6 + f] == INT32_MIN) {
+        const int group = f == 4 ? 0 : (f == 5 ? 1 : 2);
+        out[e * 6 + f] = (int32_t)(-(1 + group + 4 * nb));
+        ++nb;
+      }
+  std::memcpy(nbr, out.data(), sizeof(int32_t) * out.size());
+  return true;
+}
+
+// cube-patch frame: the reference point (1, a, b) of patch P in 3-D
+inline void patch_frame(int P, double one, double a, double b, double v[3]) {
+  static const int perm[6][3] = {{0, 1, 2}, {1, 0, 2}, {0, 1, 2}, {1, 0, 2}, {2, 1, 0}, {2, 1, 0}};
+  // components: which slot receives (one, a, b), and the signs
+  static const double sgn[6][3] = {{1, 1, 1}, {1, -1, 1}, {-1, -1, 1},
+                                   {-1, 1, 1}, {1, 1, -1}, {-1, 1, 1}};
+  double src[3] = {one, a, b};
+  for (int s = 0; s < 3; ++s) v[perm[P][s]] = sgn[P][s] * src[s];
+}
+
+// tan(-pi/4 + s (pi/2)/Nz), exactly +-1 on the patch edges
+inline double edge_tan(double s, int Nz) {
+  if (s == 0.0) return -1.0;
+  if (s == (double)Nz) return 1.0;
+  return std::tan(-kPi / 4 + s * (kPi / 2) / Nz);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Public builders
+// ---------------------------------------------------------------------------
+
+static int run_geometry(const Tables1D& t, int64_t E, const std::function<void(int64_t, Block3*)>& nodes,
+                        double* x_sp, double* detJ, double* S_fp, double* S_sp) {
+  const int N = t.N, NP = N + 1, N3 = N * N * N, NF = NP * N * N;
+#pragma omp parallel for schedule(dynamic, 32)
+  for (int64_t e = 0; e < E; ++e) {
+    Block3 X[3] = {Block3(NP, NP, NP), Block3(NP, NP, NP), Block3(NP, NP, NP)};
+    nodes(e, X);
+    element_geometry(t, X, x_sp + e * 3 * N3, detJ + e * N3, S_fp + e * 9 * NF,
+                     S_sp ? S_sp + e * 9 * N3 : nullptr);
+  }
+  return 0;
+}
+
+int shell_build(int Nz, int Nr, int p, double rb, double rt, double* x_sp, double* detJ,
+                double* S_fp, double* S_sp, int32_t* nbr) {
+  const Tables1D t = make_tables(p + 1);
+  const int NP = p + 2;
+  const int64_t E = 6LL * Nr * Nz * Nz;
+  auto decode = [=](int64_t e, int& P, int& k, int& j, int& i) {
+    i = (int)(e % Nz);
+    j = (int)((e / Nz) % Nz);
+    k = (int)((e / ((int64_t)Nz * Nz)) % Nr);
+    P = (int)(e / ((int64_t)Nz * Nz * Nr));
+  };
+  std::vector<Key> keys((size_t)E * 8);
+  for (int64_t e = 0; e < E; ++e) {
+    int P, k, j, i;
+    decode(e, P, k, j, i);
+    for (int c = 0; c < 8; ++c) {
+      const int ci = c & 1, cj = (c >> 1) & 1, ck = (c >> 2) & 1;
+      double v[3];
+      patch_frame(P, (double)Nz, (double)(2 * (i + ci) - Nz), (double)(2 * (j + cj) - Nz), v);
+      keys[e * 8 + c] = {(int32_t)std::lround(v[0]), (int32_t)std::lround(v[1]),
+                         (int32_t)std::lround(v[2]), k + ck};
+    }
+  }
+  if (!connect(E, keys, nbr)) return -1;
+  auto nodes = [&](int64_t e, Block3* X) {
+    int P, k, j, i;
+    decode(e, P, k, j, i);
+    for (int c = 0; c < NP; ++c) {
+      const double r = rb + (k + t.xf[c]) * (rt - rb) / Nr;
+      for (int b = 0; b < NP; ++b) {
+        const double tb = edge_tan(j + t.xf[b], Nz);
+        for (int a = 0; a < NP; ++a) {
+          const double ta = edge_tan(i + t.xf[a], Nz);
+          double v[3];
+          patch_frame(P, 1.0, ta, tb, v);
+          const double s = r / std::sqrt(1.0 + ta * ta + tb * tb);  // patch-local order
+          for (int q = 0; q < 3; ++q) X[q].at(a, b, c) = s * v[q];
+        }
+      }
+    }
+  };
+  return run_geometry(t, E, nodes, x_sp, detJ, S_fp, S_sp);
+}
+
+int box_build(int nx, int ny, int nz, double Lx, double Ly, double Lz, int periodic, double warp,
+              int p, double* x_sp, double* detJ, double* S_fp, double* S_sp, int32_t* nbr) {
+  const Tables1D t = make_tables(p + 1);
+  const int NP = p + 2;
+  const int n[3] = {nx, ny, nz};
+  const double L[3] = {Lx, Ly, Lz};
+  const int64_t E = (int64_t)nx * ny * nz;
+  std::vector<Key> keys((size_t)E * 8);
+  for (int64_t e = 0; e < E; ++e) {
+    const int idx[3] = {(int)(e % nx), (int)((e / nx) % ny), (int)(e / ((int64_t)nx * ny))};
+    for (int c = 0; c < 8; ++c) {
+      Key k{0, 0, 0, 0};
+      for (int d = 0; d < 3; ++d) {
+        const int v = idx[d] + ((c >> d) & 1);
+        k[d] = ((periodic >> d) & 1) ? v % n[d] : v;
+      }
+      keys[e * 8 + c] = k;
+    }
+  }
+  if (!connect(E, keys, nbr)) return -1;
+  auto nodes = [&](int64_t e, Block3* X) {
+    const int idx[3] = {(int)(e % nx), (int)((e / nx) % ny), (int)(e / ((int64_t)nx * ny))};
+    for (int c = 0; c < NP; ++c)
+      for (int b = 0; b < NP; ++b)
+        for (int a = 0; a < NP; ++a) {
+          const int ab[3] = {a, b, c};
+          double y[3];
+          for (int d = 0; d < 3; ++d) y[d] = (idx[d] + t.xf[ab[d]]) * L[d] / n[d];
+          const double s = warp * std::sin(2 * kPi * y[0] / Lx) * std::sin(2 * kPi * y[1] / Ly) *
+                           std::sin(2 * kPi * y[2] / Lz);
+          for (int d = 0; d < 3; ++d) X[d].at(a, b, c) = y[d] + s * L[d];
+        }
+  };
+  return run_geometry(t, E, nodes, x_sp, detJ, S_fp, S_sp);
+}
+
+}  // namespace sdm

@@ -1,0 +1,30 @@
+// sdm_host.hpp -- host-side setup of the spectral-difference library.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace sdm {
+
+// 1-D operators of the method for N solution points per direction
+// (paper, Sec. "Spectral Difference Method": Chebyshev-Gauss solution
+// points, Legendre flux points with both end points, bases h_i and l_i).
+struct Tables1D {
+  int N = 0;
+  std::vector<double> xs;   // [N]       solution points
+  std::vector<double> xf;   // [N+1]     flux points
+  std::vector<double> I;    // [N+1][N]  h_i(xf_f)
+  std::vector<double> D;    // [N][N+1]  l_f'(xs_i)
+  std::vector<double> L;    // [N][N+1]  l_f(xs_i)
+  std::vector<double> Dff;  // [N+1][N+1] l_f'(xf_g)
+  std::vector<double> DI;   // [N][N]    h_j'(xs_i) = (D I)_ij
+  std::vector<double> W;    // [N]       integral of h_i over [0,1]
+};
+
+Tables1D make_tables(int N);
+
+int shell_build(int Nz, int Nr, int p, double rb, double rt, double* x_sp, double* detJ,
+                double* S_fp, double* S_sp, int32_t* nbr);
+int box_build(int nx, int ny, int nz, double Lx, double Ly, double Lz, int periodic, double warp,
+              int p, double* x_sp, double* detJ, double* S_fp, double* S_sp, int32_t* nbr);
+
+}  // namespace sdm

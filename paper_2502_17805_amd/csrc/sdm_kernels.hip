@@ -1,0 +1,1045 @@
+// sdm_kernels.hip -- gfx950 kernels of the spectral-difference GLM-MHD
+// residual and fused Runge-Kutta stage (paper arXiv 2502.17805, Sec.
+// "Spectral Difference Method"), and the C ABI declared in include/sdmhd.h.
+//
+// One stage = three launches, one workgroup per element:
+//   k_traces  Q at the two end flux points of every line = the element's face
+//             traces  (only before the first stage; afterwards the previous
+//             stage's k_finish writes them)
+//   k_volume  BR1 common solution from the own and neighbour traces, gradient
+//             at the solution points (chain rule with S^d/|J|), interpolation
+//             of Q and grad Q to each flux-point family, total flux at the
+//             interior flux points, Rusanov + own half of the BR1 viscous flux
+//             at the face points (wall / Dirichlet fluxes complete), flux
+//             divergence, sources -> partial residual; writes this side's
+//             viscous normal flux for the neighbour
+//   k_finish  adds the neighbour half of the BR1 viscous flux, then either
+//             stores R or applies the Shu-Osher stage update in FP64, and
+//             writes the new state's face traces for the next stage.
+// The face coupling uses the per-element neighbour/orientation table; each
+// interior face is evaluated by both of its elements, with the symmetric face
+// normal n = (S_own - S_other)/2 so the two values are exact negatives.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sdmhd.h"
+#include "sdm_host.hpp"
+#include "sdm_physics.hpp"
+
+namespace sdm {
+
+constexpr int kNMax = 8;
+
+// ---------------------------------------------------------------------------
+// constant tables (one set per N, FP64 and FP32 copies)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct DevTab {
+  T I[kNMax + 1][kNMax];   // SP basis at FPs
+  T D[kNMax][kNMax + 1];   // FP-basis derivative at SPs
+  T L[kNMax][kNMax + 1];   // FP basis at SPs
+  T DI[kNMax][kNMax];      // derivative of the SP polynomial at SPs
+  T W[kNMax];              // quadrature weights
+};
+__constant__ DevTab<double> c_tab_d[kNMax + 1];
+__constant__ DevTab<float> c_tab_f[kNMax + 1];
+
+template <typename T>
+__device__ __forceinline__ const DevTab<T>& tab(int N);
+template <>
+__device__ __forceinline__ const DevTab<double>& tab<double>(int N) { return c_tab_d[N]; }
+template <>
+__device__ __forceinline__ const DevTab<float>& tab<float>(int N) { return c_tab_f[N]; }
+
+// ---------------------------------------------------------------------------
+// per-run descriptor (kernel argument for one run, device array for batches)
+// ---------------------------------------------------------------------------
+struct RunDesc {
+  int64_t E;
+  int64_t n_bfaces;
+  const double* x_sp;
+  const double* detJ;
+  const double* S_fp;
+  const int32_t* nbr;
+  const double* ghost;
+  const double* Q;     // state whose residual is taken
+  void* Qtr;           // [E][6][9][N2]  T
+  void* Vtr;           // [E][6][7][N2]  T
+  void* Rp;            // [E][9][N3]     T
+  double* R;           // residual output (residual mode)
+  const double* in[4]; // stage inputs
+  double alpha[4];
+  int32_t n_in;
+  int32_t write_traces;
+  double* out;         // stage output
+  double beta_dt;
+  Phys<double> P;
+};
+
+struct Launch {
+  RunDesc one;                  // used when many == nullptr
+  const RunDesc* many;          // batched runs (device)
+  const int64_t* prefix;        // [n_run + 1] element offsets of the runs
+  int32_t n_run;
+  int64_t n_work;               // total elements
+};
+
+__device__ __forceinline__ void locate(const Launch& L, int64_t w, const RunDesc*& rd, int64_t& e) {
+  if (L.many == nullptr) {
+    rd = &L.one;
+    e = w;
+    return;
+  }
+  int lo = 0, hi = L.n_run - 1;
+  while (lo < hi) {  // last run with prefix <= w
+    const int mid = (lo + hi + 1) >> 1;
+    if (L.prefix[mid] <= w) lo = mid; else hi = mid - 1;
+  }
+  rd = &L.many[lo];
+  e = w - L.prefix[lo];
+}
+
+template <typename T>
+__device__ __forceinline__ Phys<T> cvt_phys(const Phys<double>& p) {
+  Phys<T> o;
+  o.gm1 = (T)p.gm1; o.gamma = (T)p.gamma; o.Rgas = (T)p.Rgas; o.cp = (T)p.cp;
+  o.GM = (T)p.GM; o.Omega = (T)p.Omega; o.nu = (T)p.nu; o.kappa = (T)p.kappa; o.eta = (T)p.eta;
+  o.kr_scale = (T)p.kr_scale; o.kr_c0 = (T)p.kr_c0; o.kr_c1 = (T)p.kr_c1; o.kr_c2 = (T)p.kr_c2;
+  o.kr_w = (T)p.kr_w; o.c_h = (T)p.c_h; o.glm_a = (T)p.glm_a;
+  o.q_wall[0] = (T)p.q_wall[0]; o.q_wall[1] = (T)p.q_wall[1];
+  o.T_wall[0] = (T)p.T_wall[0]; o.T_wall[1] = (T)p.T_wall[1];
+  o.powell = p.powell;
+  o.wall_kind[0] = p.wall_kind[0]; o.wall_kind[1] = p.wall_kind[1];
+  o.wall_mag[0] = p.wall_mag[0]; o.wall_mag[1] = p.wall_mag[1];
+  o.wall_th[0] = p.wall_th[0]; o.wall_th[1] = p.wall_th[1];
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// index helpers
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ int sp_line(int d, int p, int q, int i) {
+  return d == 0 ? i + N * (p + N * q) : (d == 1 ? p + N * (i + N * q) : p + N * (q + N * i));
+}
+template <int N>
+__device__ __forceinline__ int fp_fam(int d, int f, int p, int q) {
+  return d == 0 ? f + (N + 1) * (p + N * q) : (d == 1 ? p + N * (f + (N + 1) * q) : p + N * (q + N * f));
+}
+template <int N>
+__device__ __forceinline__ void omap(int o, int a, int b, int& a2, int& b2) {
+  const int p = (o & 4) ? b : a, q = (o & 4) ? a : b;
+  a2 = (o & 1) ? N - 1 - p : p;
+  b2 = (o & 2) ? N - 1 - q : q;
+}
+
+template <int N>
+constexpr int block_threads() {
+  return ((N * N * N + 63) / 64) * 64 < 64 ? 64 : ((N * N * N + 63) / 64) * 64;
+}
+
+// ---------------------------------------------------------------------------
+// k_traces: face traces of Q (used before a run's first stage)
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ __launch_bounds__(block_threads<N>()) void k_traces(Launch L) {
+  constexpr int N2 = N * N, N3 = N2 * N, BS = block_threads<N>();
+  __shared__ T sQ[9 * N3];
+  const DevTab<T>& tb = tab<T>(N);
+  for (int64_t w = blockIdx.x; w < L.n_work; w += gridDim.x) {
+    const RunDesc* rd;
+    int64_t e;
+    locate(L, w, rd, e);
+    const double* Qe = rd->Q + e * 9 * N3;
+    for (int i = threadIdx.x; i < 9 * N3; i += BS) sQ[i] = (T)Qe[i];
+    __syncthreads();
+    T* tr = (T*)rd->Qtr + e * 6 * 9 * N2;
+    for (int it = threadIdx.x; it < 6 * 9 * N2; it += BS) {
+      const int ab = it % N2, fv = it / N2, v = fv % 9, f = fv / 9;
+      const int d = f >> 1, fe = (f & 1) ? N : 0;
+      T s = T(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) s += tb.I[fe][i] * sQ[v * N3 + sp_line<N>(d, ab % N, ab / N, i)];
+      tr[it] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_volume
+// ---------------------------------------------------------------------------
+template <int N, typename T, bool DIAG>
+__global__ __launch_bounds__(block_threads<N>()) void k_volume(Launch L) {
+  constexpr int N2 = N * N, N3 = N2 * N, NP = N + 1, NF = NP * N2, BS = block_threads<N>();
+  constexpr int UN = (9 * NF > 9 * 6 * N2) ? 9 * NF : 9 * 6 * N2;
+  __shared__ T sQ[9 * N3];
+  __shared__ T sG[27 * N3];
+  __shared__ T sU[UN];  // common solution on the faces, then the family fluxes
+  __shared__ double sRed[BS / 64][10];
+  static_assert(BS >= N3, "one solution point per thread");
+  const DevTab<T>& tb = tab<T>(N);
+  const int tid = threadIdx.x;
+
+  for (int64_t w = blockIdx.x; w < L.n_work; w += gridDim.x) {
+    const RunDesc* rd;
+    int64_t e;
+    locate(L, w, rd, e);
+    const Phys<T> P = cvt_phys<T>(rd->P);
+    const double* Qe = rd->Q + e * 9 * N3;
+    const double* Se = rd->S_fp + e * 9 * NF;
+    const int32_t* nb6 = rd->nbr + e * 6;
+    const T* Qtr = (const T*)rd->Qtr;
+    const bool use_kr = P.kr_scale != T(0);
+
+    // A. state into LDS; 1/|J| of this thread's solution point
+    for (int i = tid; i < 9 * N3; i += BS) sQ[i] = (T)Qe[i];
+    const T ji = tid < N3 ? T(1) / (T)rd->detJ[e * N3 + tid] : T(0);
+    __syncthreads();
+
+    // B. BR1 common solution at the 6 N^2 face points
+    for (int it = tid; it < 6 * N2; it += BS) {
+      const int f = it / N2, ab = it % N2, a = ab % N, b = ab / N;
+      const int d = f >> 1, fe = (f & 1) ? N : 0;
+      T qo[9], qc[9];
+#pragma unroll
+      for (int v = 0; v < 9; ++v) {
+        T s = T(0);
+#pragma unroll
+        for (int i = 0; i < N; ++i) s += tb.I[fe][i] * sQ[v * N3 + sp_line<N>(d, a, b, i)];
+        qo[v] = s;
+      }
+      const int32_t code = nb6[f];
+      if (code >= 0) {
+        const int64_t en = code >> 6;
+        const int fn = (code >> 3) & 7, o = code & 7;
+        int a2, b2;
+        omap<N>(o, a, b, a2, b2);
+        const T* tn = Qtr + (en * 6 + fn) * 9 * N2 + a2 + N * b2;
+#pragma unroll
+        for (int v = 0; v < 9; ++v) qc[v] = T(0.5) * (qo[v] + tn[v * N2]);
+      } else {
+        const int c2 = -code - 1, g = c2 & 3;
+        const int64_t bf = c2 >> 2;
+        if (g == 2 || P.wall_kind[g] == 1) {
+          const double* gh = rd->ghost + bf * 9 * N2 + ab;
+#pragma unroll
+          for (int v = 0; v < 9; ++v) qc[v] = T(0.5) * (qo[v] + (T)gh[v * N2]);
+        } else {
+          const int idx = fp_fam<N>(d, fe, a, b);
+          const T sg = (f & 1) ? T(1) : T(-1);
+          T n[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) n[c] = sg * (T)Se[(d * 3 + c) * NF + idx];
+          const T inn = T(1) / sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+          const T nh[3] = {n[0] * inn, n[1] * inn, n[2] * inn};
+          wall_common(qo, nh, g, P, qc);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 9; ++v) sU[(f * 9 + v) * N2 + ab] = qc[v];
+    }
+    __syncthreads();
+
+    // C. gradient at the solution points
+    for (int sp = tid; sp < N3; sp += BS) {
+      const int ia[3] = {sp % N, (sp / N) % N, sp / N2};
+      T Sj[3][3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int p = d == 0 ? ia[1] : ia[0], q = d == 2 ? ia[1] : ia[2], i = ia[d];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          T s = T(0);
+#pragma unroll
+          for (int f = 0; f < NP; ++f) s += tb.L[i][f] * (T)Se[(d * 3 + c) * NF + fp_fam<N>(d, f, p, q)];
+          Sj[d][c] = s * ji;
+        }
+      }
+      T g27[27];
+#pragma unroll
+      for (int k = 0; k < 27; ++k) g27[k] = T(0);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int p = d == 0 ? ia[1] : ia[0], q = d == 2 ? ia[1] : ia[2], i = ia[d];
+        const int pq = p + N * q;
+#pragma unroll
+        for (int v = 0; v < 9; ++v) {
+          T der = T(0), t0 = T(0), tN = T(0);
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            const T qv = sQ[v * N3 + sp_line<N>(d, p, q, j)];
+            der += tb.DI[i][j] * qv;
+            t0 += tb.I[0][j] * qv;
+            tN += tb.I[N][j] * qv;
+          }
+          der += tb.D[i][0] * (sU[((2 * d) * 9 + v) * N2 + pq] - t0) +
+                 tb.D[i][N] * (sU[((2 * d + 1) * 9 + v) * N2 + pq] - tN);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) g27[v * 3 + c] += Sj[d][c] * der;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 27; ++k) sG[k * N3 + sp] = g27[k];
+    }
+    __syncthreads();
+
+    if (DIAG) {
+      // per-element diagnostics: W^3 |J|-weighted sums, maxima, NaN flag
+      double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int sp = tid; sp < N3; sp += BS) {
+        const int a = sp % N, b = (sp / N) % N, c = sp / N2;
+        const double wq = (double)tb.W[a] * (double)tb.W[b] * (double)tb.W[c] * rd->detJ[e * N3 + sp];
+        const double* q = Qe + sp;
+        const double rho = q[0];
+        const double m2 = q[N3] * q[N3] + q[2 * N3] * q[2 * N3] + q[3 * N3] * q[3 * N3];
+        const double b2 = q[5 * N3] * q[5 * N3] + q[6 * N3] * q[6 * N3] + q[7 * N3] * q[7 * N3];
+        const double db = (double)sG[15 * N3 + sp] + (double)sG[19 * N3 + sp] + (double)sG[23 * N3 + sp];
+        acc[0] += wq;
+        acc[1] += wq * rho;
+        acc[2] += wq * q[4 * N3];
+        acc[3] += wq * 0.5 * m2 / rho;
+        acc[4] += wq * 0.5 * b2;
+        acc[5] = fmax(acc[5], fabs(db));
+        acc[6] += wq * db * db;
+        acc[7] = fmax(acc[7], fabs(q[8 * N3]));
+        bool bad = false;
+        for (int v = 0; v < 9; ++v) bad = bad || !isfinite(q[v * N3]);
+        acc[8] = bad ? 1.0 : acc[8];
+      }
+      // wave reduction in a fixed order, then across waves
+      for (int k = 0; k < 9; ++k) {
+        double x = acc[k];
+        for (int off = 32; off > 0; off >>= 1) {
+          const double y = __shfl_down(x, off, 64);
+          x = (k == 5 || k == 7 || k == 8) ? fmax(x, y) : x + y;
+        }
+        if ((tid & 63) == 0) sRed[tid >> 6][k] = x;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double out[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int wv = 0; wv < BS / 64; ++wv)
+          for (int k = 0; k < 9; ++k)
+            out[k] = (k == 5 || k == 7 || k == 8) ? fmax(out[k], sRed[wv][k]) : out[k] + sRed[wv][k];
+        double* dst = (double*)rd->Rp + e * 10;
+        for (int k = 0; k < 10; ++k) dst[k] = out[k];
+      }
+      __syncthreads();
+      continue;
+    }
+
+    // D. per family: fluxes at the flux points, then the divergence
+    T div[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) div[v] = T(0);
+    T* Vtr = (T*)rd->Vtr;
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+      for (int it = tid; it < NF; it += BS) {
+        const int f = it % NP, line = it / NP, p = line % N, q = line / N;
+        T qf[9], gf[27];
+        T kf = T(0);
+#pragma unroll
+        for (int v = 0; v < 9; ++v) qf[v] = T(0);
+#pragma unroll
+        for (int k = 0; k < 27; ++k) gf[k] = T(0);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          const T w = tb.I[f][i];
+          const int s = sp_line<N>(d, p, q, i);
+#pragma unroll
+          for (int v = 0; v < 9; ++v) qf[v] += w * sQ[v * N3 + s];
+#pragma unroll
+          for (int k = 0; k < 27; ++k) gf[k] += w * sG[k * N3 + s];
+        }
+        if (use_kr) {  // radiative diffusivity sampled at the SPs, interpolated like Q
+          for (int i = 0; i < N; ++i) {
+            const int s = sp_line<N>(d, p, q, i);
+            const T x[3] = {(T)rd->x_sp[(e * 3 + 0) * N3 + s], (T)rd->x_sp[(e * 3 + 1) * N3 + s],
+                            (T)rd->x_sp[(e * 3 + 2) * N3 + s]};
+            kf += tb.I[f][i] * kappa_r(x, P);
+          }
+        }
+        const int fi = fp_fam<N>(d, f, p, q);
+        T Sd[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Sd[c] = (T)Se[(d * 3 + c) * NF + fi];
+        T F[9];
+        if (f != 0 && f != N) {
+          T Fv[7];
+          ViscLocal<T> vl;
+          viscous_local(qf, gf, kf, P, vl);
+          flux_inviscid(qf, Sd, P, F);
+          flux_viscous7(vl, Sd, P, Fv);
+#pragma unroll
+          for (int c = 0; c < 7; ++c) F[1 + c] -= Fv[c];
+        } else {
+          const int face = 2 * d + (f == N ? 1 : 0);
+          const T sg = f == N ? T(1) : T(-1);
+          const T no[3] = {sg * Sd[0], sg * Sd[1], sg * Sd[2]};
+          const int32_t code = nb6[face];
+          if (code >= 0) {
+            const int64_t en = code >> 6;
+            const int fn = (code >> 3) & 7, o = code & 7;
+            int a2, b2;
+            omap<N>(o, p, q, a2, b2);
+            const T* tn = Qtr + (en * 6 + fn) * 9 * N2 + a2 + N * b2;
+            T qn[9];
+#pragma unroll
+            for (int v = 0; v < 9; ++v) qn[v] = tn[v * N2];
+            const int dn = fn >> 1;
+            const int fin = fp_fam<N>(dn, (fn & 1) ? N : 0, a2, b2);
+            const T sgn = (fn & 1) ? T(1) : T(-1);
+            const double* Sen = rd->S_fp + en * 9 * NF;
+            T n[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) n[c] = T(0.5) * (no[c] - sgn * (T)Sen[(dn * 3 + c) * NF + fin]);
+            rusanov(qf, qn, n, P, F);
+            T Fv[7];
+            ViscLocal<T> vl;
+            viscous_local(qf, gf, kf, P, vl);
+            flux_viscous7(vl, n, P, Fv);
+            T* vt = Vtr + (e * 6 + face) * 7 * N2 + p + N * q;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) {
+              vt[c * N2] = Fv[c];
+              F[1 + c] -= T(0.5) * Fv[c];
+            }
+          } else {
+            const int c2 = -code - 1, g = c2 & 3;
+            const int64_t bf = c2 >> 2;
+            if (g == 2 || P.wall_kind[g] == 1) {
+              const double* gh = rd->ghost + bf * 9 * N2 + p + N * q;
+              T qg[9];
+#pragma unroll
+              for (int v = 0; v < 9; ++v) qg[v] = (T)gh[v * N2];
+              rusanov(qf, qg, no, P, F);
+              T Fv1[7], Fv2[7];
+              ViscLocal<T> vl;
+              viscous_local(qf, gf, kf, P, vl);
+              flux_viscous7(vl, no, P, Fv1);
+              viscous_local(qg, gf, kf, P, vl);
+              flux_viscous7(vl, no, P, Fv2);
+#pragma unroll
+              for (int c = 0; c < 7; ++c) F[1 + c] -= T(0.5) * (Fv1[c] + Fv2[c]);
+            } else {
+              wall_flux(qf, gf, kf, no, g, P, F);
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < 9; ++v) F[v] *= sg;
+        }
+#pragma unroll
+        for (int v = 0; v < 9; ++v) sU[v * NF + it] = F[v];
+      }
+      __syncthreads();
+      for (int sp = tid; sp < N3; sp += BS) {
+        const int ia[3] = {sp % N, (sp / N) % N, sp / N2};
+        const int p = d == 0 ? ia[1] : ia[0], q = d == 2 ? ia[1] : ia[2], i = ia[d];
+        const int base = (p + N * q) * NP;
+#pragma unroll
+        for (int v = 0; v < 9; ++v) {
+          T s = T(0);
+#pragma unroll
+          for (int f = 0; f < NP; ++f) s += tb.D[i][f] * sU[v * NF + base + f];
+          div[v] += s;  // BS >= N3: each thread owns at most one solution point
+        }
+      }
+      __syncthreads();
+    }
+
+    // E. sources (Eq. "M") and the partial residual -div/|J| + M
+    for (int sp = tid; sp < N3; sp += BS) {
+      T q[9];
+#pragma unroll
+      for (int v = 0; v < 9; ++v) q[v] = sQ[v * N3 + sp];
+      const T x[3] = {(T)rd->x_sp[(e * 3 + 0) * N3 + sp], (T)rd->x_sp[(e * 3 + 1) * N3 + sp],
+                      (T)rd->x_sp[(e * 3 + 2) * N3 + sp]};
+      T gv[3] = {T(0), T(0), T(0)};
+      if (P.GM != T(0)) {
+        const T r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+        const T s = -P.GM / (r2 * sqrt(r2));
+        gv[0] = s * x[0]; gv[1] = s * x[1]; gv[2] = s * x[2];
+      }
+      const T ir = T(1) / q[0];
+      const T db = P.powell ? sG[15 * N3 + sp] + sG[19 * N3 + sp] + sG[23 * N3 + sp] : T(0);
+      const T uB = (q[1] * q[5] + q[2] * q[6] + q[3] * q[7]) * ir;
+      T M[9];
+      M[0] = T(0);
+      M[1] = q[0] * gv[0] + T(2) * P.Omega * q[2] - db * q[5];
+      M[2] = q[0] * gv[1] - T(2) * P.Omega * q[1] - db * q[6];
+      M[3] = q[0] * gv[2] - db * q[7];
+      M[4] = q[1] * gv[0] + q[2] * gv[1] + q[3] * gv[2] - db * uB;
+      M[5] = -db * q[1] * ir;
+      M[6] = -db * q[2] * ir;
+      M[7] = -db * q[3] * ir;
+      M[8] = -P.glm_a * q[8];
+      T* rp = (T*)rd->Rp + e * 9 * N3 + sp;
+#pragma unroll
+      for (int v = 0; v < 9; ++v) rp[v * N3] = M[v] - div[v] * ji;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_finish: neighbour half of the viscous common flux, then R or the stage
+// ---------------------------------------------------------------------------
+template <int N, typename T, bool STAGE>
+__global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
+  constexpr int N2 = N * N, N3 = N2 * N, NP = N + 1, BS = block_threads<N>();
+  __shared__ T sV[6 * 7 * N2];
+  __shared__ double sOut[STAGE ? 9 * N3 : 1];
+  const DevTab<T>& tb = tab<T>(N);
+  const DevTab<double>& tbd = tab<double>(N);
+  const int tid = threadIdx.x;
+  for (int64_t w = blockIdx.x; w < L.n_work; w += gridDim.x) {
+    const RunDesc* rd;
+    int64_t e;
+    locate(L, w, rd, e);
+    const int32_t* nb6 = rd->nbr + e * 6;
+    const T* Vtr = (const T*)rd->Vtr;
+    for (int it = tid; it < 6 * N2; it += BS) {
+      const int f = it / N2, ab = it % N2;
+      const int32_t code = nb6[f];
+      if (code >= 0) {
+        const int64_t en = code >> 6;
+        const int fn = (code >> 3) & 7, o = code & 7;
+        int a2, b2;
+        omap<N>(o, ab % N, ab / N, a2, b2);
+        const T* src = Vtr + (en * 6 + fn) * 7 * N2 + a2 + N * b2;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) sV[(f * 7 + c) * N2 + ab] = src[c * N2];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) sV[(f * 7 + c) * N2 + ab] = T(0);
+      }
+    }
+    __syncthreads();
+    for (int sp = tid; sp < N3; sp += BS) {
+      const int ia[3] = {sp % N, (sp / N) % N, sp / N2};
+      T corr[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int p = d == 0 ? ia[1] : ia[0], q = d == 2 ? ia[1] : ia[2], i = ia[d];
+        const int pq = p + N * q;
+        const T w0 = T(-0.5) * tb.D[i][0], wN = T(0.5) * tb.D[i][N];
+#pragma unroll
+        for (int c = 0; c < 7; ++c)
+          corr[c] += w0 * sV[((2 * d) * 7 + c) * N2 + pq] + wN * sV[((2 * d + 1) * 7 + c) * N2 + pq];
+      }
+      const T ji = T(1) / (T)rd->detJ[e * N3 + sp];
+      const T* rp = (const T*)rd->Rp + e * 9 * N3 + sp;
+      double Rv[9];
+#pragma unroll
+      for (int v = 0; v < 9; ++v) {
+        const T c = (v >= 1 && v <= 7) ? corr[v - 1] : T(0);
+        Rv[v] = (double)(rp[v * N3] - c * ji);
+      }
+      if (!STAGE) {
+        double* R = rd->R + e * 9 * N3 + sp;
+#pragma unroll
+        for (int v = 0; v < 9; ++v) R[v * N3] = Rv[v];
+      } else {
+        // Shu-Osher stage in FP64: sum_k alpha_k u_k + beta dt R
+        double u[9];
+#pragma unroll
+        for (int v = 0; v < 9; ++v) u[v] = rd->beta_dt * Rv[v];
+        for (int k = 0; k < rd->n_in; ++k) {
+          const double a = rd->alpha[k];
+          const double* src = rd->in[k] + e * 9 * N3 + sp;
+#pragma unroll
+          for (int v = 0; v < 9; ++v) u[v] += a * src[v * N3];
+        }
+#pragma unroll
+        for (int v = 0; v < 9; ++v) sOut[v * N3 + sp] = u[v];
+      }
+    }
+    if (STAGE) {
+      __syncthreads();
+      double* out = rd->out + e * 9 * N3;
+      for (int i = tid; i < 9 * N3; i += BS) out[i] = sOut[i];
+      if (rd->write_traces) {
+        T* tr = (T*)rd->Qtr + e * 6 * 9 * N2;
+        for (int it = tid; it < 6 * 9 * N2; it += BS) {
+          const int ab = it % N2, fv = it / N2, v = fv % 9, f = fv / 9;
+          const int d = f >> 1, fe = (f & 1) ? N : 0;
+          T s = T(0);
+#pragma unroll
+          for (int i = 0; i < N; ++i) s += tb.I[fe][i] * (T)sOut[v * N3 + sp_line<N>(d, ab % N, ab / N, i)];
+          tr[it] = s;
+        }
+      }
+      (void)tbd;
+    }
+    __syncthreads();
+  }
+  (void)NP;
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics reduction (one block, fixed order)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_diag_reduce(const double* part, int64_t E, double* out) {
+  __shared__ double s[256][9];
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t e = threadIdx.x; e < E; e += 256)
+    for (int k = 0; k < 9; ++k) {
+      const double x = part[e * 10 + k];
+      acc[k] = (k == 5 || k == 7 || k == 8) ? fmax(acc[k], x) : acc[k] + x;
+    }
+  for (int k = 0; k < 9; ++k) s[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = 0; t < 256; ++t)
+      for (int k = 0; k < 9; ++k) r[k] = (k == 5 || k == 7 || k == 8) ? fmax(r[k], s[t][k]) : r[k] + s[t][k];
+    const double V = r[0];
+    out[0] = V;
+    out[1] = r[1];
+    out[2] = r[2];
+    out[3] = r[3] / V;
+    out[4] = r[4] / V;
+    out[5] = r[5];
+    out[6] = sqrt(r[6] / V);
+    out[7] = r[7];
+    out[8] = r[8];
+    for (int k = 9; k < 16; ++k) out[k] = 0.0;
+  }
+}
+
+}  // namespace sdm
+
+// ===========================================================================
+// host side: contexts, launches, C ABI
+// ===========================================================================
+using namespace sdm;
+
+namespace {
+
+thread_local std::string g_err;
+
+sdm_status fail(sdm_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(SDM_EHIP, std::string(#expr ": ") + hipGetErrorString(_e));          \
+  } while (0)
+
+std::mutex g_tab_mu;
+bool g_tab_ready[64] = {false};
+
+sdm_status upload_tables(int device) {
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  if (device < 0 || device >= 64) return fail(SDM_EINVAL, "device index out of range");
+  if (g_tab_ready[device]) return SDM_OK;
+  std::vector<DevTab<double>> td(kNMax + 1);
+  std::vector<DevTab<float>> tf(kNMax + 1);
+  std::memset(td.data(), 0, sizeof(DevTab<double>) * td.size());
+  std::memset(tf.data(), 0, sizeof(DevTab<float>) * tf.size());
+  for (int N = 2; N <= kNMax; ++N) {
+    Tables1D t = make_tables(N);
+    for (int f = 0; f <= N; ++f)
+      for (int i = 0; i < N; ++i) td[N].I[f][i] = t.I[f * N + i];
+    for (int i = 0; i < N; ++i)
+      for (int f = 0; f <= N; ++f) {
+        td[N].D[i][f] = t.D[i * (N + 1) + f];
+        td[N].L[i][f] = t.L[i * (N + 1) + f];
+      }
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) td[N].DI[i][j] = t.DI[i * N + j];
+    for (int i = 0; i < N; ++i) td[N].W[i] = t.W[i];
+    const double* s = (const double*)&td[N];
+    float* d = (float*)&tf[N];
+    for (size_t k = 0; k < sizeof(DevTab<double>) / sizeof(double); ++k) d[k] = (float)s[k];
+  }
+  HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_tab_d), td.data(), sizeof(DevTab<double>) * td.size()));
+  HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_tab_f), tf.data(), sizeof(DevTab<float>) * tf.size()));
+  g_tab_ready[device] = true;
+  return SDM_OK;
+}
+
+Phys<double> to_phys(const sdm_params* p) {
+  Phys<double> o;
+  o.gamma = p->gamma;
+  o.gm1 = p->gamma - 1.0;
+  o.Rgas = p->Rgas;
+  o.cp = p->gamma * p->Rgas / (p->gamma - 1.0);
+  o.GM = p->GM; o.Omega = p->Omega; o.nu = p->nu; o.kappa = p->kappa; o.eta = p->eta;
+  o.kr_scale = p->kr_scale; o.kr_c0 = p->kr_c0; o.kr_c1 = p->kr_c1; o.kr_c2 = p->kr_c2;
+  o.kr_w = p->kr_omega_per_r;
+  o.c_h = p->c_h; o.glm_a = p->glm_a;
+  o.q_wall[0] = p->q_wall[0]; o.q_wall[1] = p->q_wall[1];
+  o.T_wall[0] = p->T_wall[0]; o.T_wall[1] = p->T_wall[1];
+  o.powell = p->powell;
+  for (int g = 0; g < 2; ++g) {
+    o.wall_kind[g] = p->wall_kind[g];
+    o.wall_mag[g] = p->wall_mag[g];
+    o.wall_th[g] = p->wall_th[g];
+  }
+  return o;
+}
+
+}  // namespace
+
+struct sdm_ctx {
+  int device = 0;
+  int p = 5;
+  int N = 6;
+  int arith = 0;
+  bool bound = false;
+  sdm_mesh mesh{};
+  int64_t n_group[3] = {0, 0, 0};  // boundary faces per group
+  // optional per-kernel timing: events recorded around every launch
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> marks;  // (kernel id, start event index)
+};
+
+namespace {
+
+size_t real_size(const sdm_ctx* c) { return c->arith ? sizeof(float) : sizeof(double); }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// workspace pieces: Qtr | Vtr | Rp (Rp also holds diagnostics partials)
+void ws_layout(const sdm_ctx* c, size_t off[4]) {
+  const int64_t E = c->mesh.n_elem;
+  const int N = c->N;
+  const size_t rs = real_size(c);
+  const size_t qtr = align256((size_t)E * 6 * 9 * N * N * rs);
+  const size_t vtr = align256((size_t)E * 6 * 7 * N * N * rs);
+  const size_t rp = align256(std::max((size_t)E * 9 * N * N * N * rs, (size_t)E * 10 * sizeof(double)));
+  off[0] = 0;
+  off[1] = qtr;
+  off[2] = qtr + vtr;
+  off[3] = qtr + vtr + rp;
+}
+
+sdm_status check_params(const sdm_ctx* c, const sdm_params* p) {
+  if (!p) return fail(SDM_EINVAL, "params is NULL");
+  if (!(p->gamma > 1.0) || !(p->Rgas > 0.0)) return fail(SDM_EINVAL, "gamma must exceed 1 and Rgas be positive");
+  for (int g = 0; g < 2; ++g) {
+    if (p->wall_kind[g] < 0 || p->wall_kind[g] > 1 || p->wall_mag[g] < 0 || p->wall_mag[g] > 1 ||
+        p->wall_th[g] < 0 || p->wall_th[g] > 1)
+      return fail(SDM_EINVAL, "wall selector out of range");
+  }
+  const bool need_ghost = c->n_group[2] > 0 || (c->n_group[0] > 0 && p->wall_kind[0] == 1) ||
+                          (c->n_group[1] > 0 && p->wall_kind[1] == 1);
+  if (need_ghost && !p->ghost) return fail(SDM_EINVAL, "Dirichlet faces present but ghost is NULL");
+  return SDM_OK;
+}
+
+RunDesc make_desc(const sdm_ctx* c, const sdm_params* p, const double* Q, void* ws) {
+  RunDesc r;
+  std::memset(&r, 0, sizeof r);
+  size_t off[4];
+  ws_layout(c, off);
+  r.E = c->mesh.n_elem;
+  r.n_bfaces = c->mesh.n_bfaces;
+  r.x_sp = c->mesh.x_sp;
+  r.detJ = c->mesh.detJ;
+  r.S_fp = c->mesh.S_fp;
+  r.nbr = c->mesh.nbr;
+  r.ghost = p ? p->ghost : nullptr;
+  r.Q = Q;
+  r.Qtr = (char*)ws + off[0];
+  r.Vtr = (char*)ws + off[1];
+  r.Rp = (char*)ws + off[2];
+  if (p) r.P = to_phys(p);
+  return r;
+}
+
+template <int N, typename T>
+hipError_t launch_all(int which, const Launch& L, hipStream_t s) {
+  constexpr int BS = block_threads<N>();
+  const unsigned grid = (unsigned)std::min<int64_t>(L.n_work, (int64_t)1 << 30);
+  if (L.n_work == 0) return hipSuccess;
+  switch (which) {
+    case 0: hipLaunchKernelGGL((k_traces<N, T>), dim3(grid), dim3(BS), 0, s, L); break;
+    case 1: hipLaunchKernelGGL((k_volume<N, T, false>), dim3(grid), dim3(BS), 0, s, L); break;
+    case 2: hipLaunchKernelGGL((k_volume<N, T, true>), dim3(grid), dim3(BS), 0, s, L); break;
+    case 3: hipLaunchKernelGGL((k_finish<N, T, false>), dim3(grid), dim3(BS), 0, s, L); break;
+    case 4: hipLaunchKernelGGL((k_finish<N, T, true>), dim3(grid), dim3(BS), 0, s, L); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_N(int N, int which, const Launch& L, hipStream_t s) {
+  switch (N) {
+    case 2: return launch_all<2, T>(which, L, s);
+    case 3: return launch_all<3, T>(which, L, s);
+    case 4: return launch_all<4, T>(which, L, s);
+    case 5: return launch_all<5, T>(which, L, s);
+    case 6: return launch_all<6, T>(which, L, s);
+    case 7: return launch_all<7, T>(which, L, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+sdm_status run(sdm_ctx* c, int which, const Launch& L, hipStream_t s) {
+  size_t e0 = 0;
+  if (c->prof) {
+    while (c->ev.size() < c->ev_used + 2) {
+      hipEvent_t h;
+      HIP_TRY(hipEventCreate(&h));
+      c->ev.push_back(h);
+    }
+    e0 = c->ev_used;
+    c->ev_used += 2;
+    HIP_TRY(hipEventRecord(c->ev[e0], s));
+  }
+  hipError_t e = c->arith ? dispatch_N<float>(c->N, which, L, s) : dispatch_N<double>(c->N, which, L, s);
+  if (e != hipSuccess) return fail(SDM_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  if (c->prof) {
+    HIP_TRY(hipEventRecord(c->ev[e0 + 1], s));
+    c->marks.emplace_back(which, e0);
+  }
+  return SDM_OK;
+}
+
+Launch single(const RunDesc& r) {
+  Launch L;
+  std::memset(&L, 0, sizeof L);
+  L.one = r;
+  L.many = nullptr;
+  L.prefix = nullptr;
+  L.n_run = 1;
+  L.n_work = r.E;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sdm_last_error(void) { return g_err.c_str(); }
+
+const char* sdm_version(void) { return "sdmhd-gfx950 0.1"; }
+
+sdm_status sdm_shell_sizes(int Nz, int Nr, int64_t* n_elem, int64_t* n_bfaces) {
+  if (Nz < 1 || Nr < 1 || !n_elem) return fail(SDM_EINVAL, "shell sizes: Nz, Nr >= 1 and n_elem required");
+  *n_elem = 6LL * Nz * Nz * Nr;
+  if (n_bfaces) *n_bfaces = 12LL * Nz * Nz;
+  return SDM_OK;
+}
+
+sdm_status sdm_shell_build(int Nz, int Nr, int p, double rb, double rt, double* x_sp, double* detJ,
+                           double* S_fp, double* S_sp, int32_t* nbr) {
+  if (Nz < 1 || Nr < 1 || p < 1 || p > kNMax - 1 || !(rb > 0) || !(rt > rb))
+    return fail(SDM_EINVAL, "shell build: need Nz, Nr >= 1, 1 <= p <= 7, 0 < rb < rt");
+  if (!x_sp || !detJ || !S_fp || !nbr) return fail(SDM_EINVAL, "shell build: NULL output");
+  if (shell_build(Nz, Nr, p, rb, rt, x_sp, detJ, S_fp, S_sp, nbr)) return fail(SDM_EINVAL, "shell connectivity failed");
+  return SDM_OK;
+}
+
+sdm_status sdm_box_sizes(int nx, int ny, int nz, int periodic, int64_t* n_elem, int64_t* n_bfaces) {
+  const int n[3] = {nx, ny, nz};
+  for (int d = 0; d < 3; ++d)
+    if (n[d] < 1 || (((periodic >> d) & 1) && n[d] < 3))
+      return fail(SDM_EINVAL, "box: >= 1 element per direction, >= 3 in periodic ones");
+  if (!n_elem) return fail(SDM_EINVAL, "box sizes: n_elem is NULL");
+  *n_elem = (int64_t)nx * ny * nz;
+  if (n_bfaces) {
+    int64_t nb = 0;
+    if (!(periodic & 1)) nb += 2LL * ny * nz;
+    if (!(periodic & 2)) nb += 2LL * nx * nz;
+    if (!(periodic & 4)) nb += 2LL * nx * ny;
+    *n_bfaces = nb;
+  }
+  return SDM_OK;
+}
+
+sdm_status sdm_box_build(int nx, int ny, int nz, double Lx, double Ly, double Lz, int periodic, double warp,
+                         int p, double* x_sp, double* detJ, double* S_fp, double* S_sp, int32_t* nbr) {
+  int64_t E;
+  sdm_status st = sdm_box_sizes(nx, ny, nz, periodic, &E, nullptr);
+  if (st != SDM_OK) return st;
+  if (p < 1 || p > kNMax - 1 || !(Lx > 0) || !(Ly > 0) || !(Lz > 0))
+    return fail(SDM_EINVAL, "box build: need 1 <= p <= 7 and positive lengths");
+  if (!x_sp || !detJ || !S_fp || !nbr) return fail(SDM_EINVAL, "box build: NULL output");
+  if (box_build(nx, ny, nz, Lx, Ly, Lz, periodic, warp, p, x_sp, detJ, S_fp, S_sp, nbr))
+    return fail(SDM_EINVAL, "box connectivity failed");
+  return SDM_OK;
+}
+
+sdm_status sdm_tables(int p, double* xs, double* xf, double* I, double* D, double* W) {
+  if (p < 1 || p > kNMax - 1) return fail(SDM_EINVAL, "tables: 1 <= p <= 7");
+  if (!xs || !xf || !I || !D || !W) return fail(SDM_EINVAL, "tables: NULL output");
+  Tables1D t = make_tables(p + 1);
+  std::copy(t.xs.begin(), t.xs.end(), xs);
+  std::copy(t.xf.begin(), t.xf.end(), xf);
+  std::copy(t.I.begin(), t.I.end(), I);
+  std::copy(t.D.begin(), t.D.end(), D);
+  std::copy(t.W.begin(), t.W.end(), W);
+  return SDM_OK;
+}
+
+sdm_status sdm_create(int device, int p, int arith, sdm_ctx** out) {
+  if (!out) return fail(SDM_EINVAL, "create: out is NULL");
+  if (p < 1 || p > 6) return fail(SDM_EUNSUPPORTED, "create: the device kernels support 1 <= p <= 6");
+  if (arith != 0 && arith != 1) return fail(SDM_EINVAL, "create: arith must be 0 (FP64) or 1 (mixed)");
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(SDM_EINVAL, "create: no such device");
+  HIP_TRY(hipSetDevice(device));
+  sdm_status st = upload_tables(device);
+  if (st != SDM_OK) return st;
+  sdm_ctx* c = new sdm_ctx;
+  c->device = device;
+  c->p = p;
+  c->N = p + 1;
+  c->arith = arith;
+  *out = c;
+  return SDM_OK;
+}
+
+sdm_status sdm_destroy(sdm_ctx* c) {
+  if (c) {
+    for (hipEvent_t h : c->ev) (void)hipEventDestroy(h);
+  }
+  delete c;
+  return SDM_OK;
+}
+
+sdm_status sdm_profile_enable(sdm_ctx* c, int enable) {
+  if (!c) return fail(SDM_EINVAL, "profile_enable: NULL context");
+  c->prof = enable != 0;
+  c->ev_used = 0;
+  c->marks.clear();
+  return SDM_OK;
+}
+
+sdm_status sdm_profile_read(sdm_ctx* c, double* ms, int64_t* count) {
+  if (!c || !ms || !count) return fail(SDM_EINVAL, "profile_read: NULL argument");
+  for (int k = 0; k < 8; ++k) { ms[k] = 0.0; count[k] = 0; }
+  HIP_TRY(hipSetDevice(c->device));
+  for (const auto& m : c->marks) {
+    HIP_TRY(hipEventSynchronize(c->ev[m.second + 1]));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, c->ev[m.second], c->ev[m.second + 1]));
+    ms[m.first] += t;
+    count[m.first] += 1;
+  }
+  c->ev_used = 0;
+  c->marks.clear();
+  return SDM_OK;
+}
+
+sdm_status sdm_mesh_bind(sdm_ctx* c, const sdm_mesh* m) {
+  if (!c || !m) return fail(SDM_EINVAL, "mesh_bind: NULL argument");
+  if (m->n_elem < 1 || m->n_bfaces < 0 || m->n_elem >= ((int64_t)1 << 25))
+    return fail(SDM_EINVAL, "mesh_bind: 1 <= n_elem < 2^25 required");
+  if (!m->x_sp || !m->detJ || !m->S_fp || !m->nbr) return fail(SDM_EINVAL, "mesh_bind: NULL array");
+  // validate the neighbour table on the host: every code must decode into range
+  std::vector<int32_t> nb((size_t)m->n_elem * 6);
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipMemcpy(nb.data(), m->nbr, sizeof(int32_t) * nb.size(), hipMemcpyDeviceToHost));
+  int64_t ng[3] = {0, 0, 0};
+  for (int64_t i = 0; i < (int64_t)nb.size(); ++i) {
+    const int32_t code = nb[i];
+    if (code >= 0) {
+      const int64_t en = code >> 6;
+      const int fn = (code >> 3) & 7;
+      if (en >= m->n_elem || fn > 5) return fail(SDM_EINVAL, "mesh_bind: neighbour code out of range");
+    } else {
+      const int64_t c2 = -(int64_t)code - 1;
+      const int g = (int)(c2 & 3);
+      const int64_t bf = c2 >> 2;
+      if (g > 2 || bf >= m->n_bfaces) return fail(SDM_EINVAL, "mesh_bind: boundary code out of range");
+      ++ng[g];
+    }
+  }
+  c->mesh = *m;
+  for (int g = 0; g < 3; ++g) c->n_group[g] = ng[g];
+  c->bound = true;
+  return SDM_OK;
+}
+
+sdm_status sdm_workspace_size(const sdm_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(SDM_EINVAL, "workspace_size: NULL argument");
+  if (!c->bound) return fail(SDM_ESTATE, "workspace_size: no mesh bound");
+  size_t off[4];
+  ws_layout(c, off);
+  *bytes = off[3];
+  return SDM_OK;
+}
+
+sdm_status sdm_residual(sdm_ctx* c, const sdm_params* p, const double* Q, double* R, void* ws, void* stream) {
+  if (!c || !Q || !R || !ws) return fail(SDM_EINVAL, "residual: NULL argument");
+  if (!c->bound) return fail(SDM_ESTATE, "residual: no mesh bound");
+  sdm_status st = check_params(c, p);
+  if (st != SDM_OK) return st;
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  RunDesc r = make_desc(c, p, Q, ws);
+  r.R = R;
+  Launch L = single(r);
+  if ((st = run(c, 0, L, s)) != SDM_OK) return st;
+  if ((st = run(c, 1, L, s)) != SDM_OK) return st;
+  return run(c, 3, L, s);
+}
+
+sdm_status sdm_rk_stage(sdm_ctx* c, const sdm_params* p, double* const* regs, int n_regs,
+                        const sdm_stage* stg, double dt, void* ws, void* stream) {
+  if (!c || !regs || !stg || !ws) return fail(SDM_EINVAL, "rk_stage: NULL argument");
+  if (!c->bound) return fail(SDM_ESTATE, "rk_stage: no mesh bound");
+  if (n_regs < 1 || n_regs > 16) return fail(SDM_EINVAL, "rk_stage: 1 <= n_regs <= 16");
+  if (stg->n_in < 0 || stg->n_in > 4) return fail(SDM_EINVAL, "rk_stage: 0 <= n_in <= 4");
+  auto okreg = [&](int i) { return i >= 0 && i < n_regs && regs[i] != nullptr; };
+  if (!okreg(stg->cur) || !okreg(stg->out)) return fail(SDM_EINVAL, "rk_stage: register index out of range");
+  for (int k = 0; k < stg->n_in; ++k)
+    if (!okreg(stg->in_idx[k])) return fail(SDM_EINVAL, "rk_stage: input register out of range");
+  sdm_status st = check_params(c, p);
+  if (st != SDM_OK) return st;
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  RunDesc r = make_desc(c, p, regs[stg->cur], ws);
+  for (int k = 0; k < stg->n_in; ++k) {
+    r.in[k] = regs[stg->in_idx[k]];
+    r.alpha[k] = stg->alpha[k];
+  }
+  r.n_in = stg->n_in;
+  r.out = regs[stg->out];
+  r.beta_dt = stg->beta * dt;
+  r.write_traces = 1;
+  Launch L = single(r);
+  if (!stg->traces_valid && (st = run(c, 0, L, s)) != SDM_OK) return st;
+  if ((st = run(c, 1, L, s)) != SDM_OK) return st;
+  return run(c, 4, L, s);
+}
+
+sdm_status sdm_diagnostics(sdm_ctx* c, const sdm_params* p, const double* Q, double* out, void* ws,
+                           void* stream) {
+  if (!c || !Q || !out || !ws) return fail(SDM_EINVAL, "diagnostics: NULL argument");
+  if (!c->bound) return fail(SDM_ESTATE, "diagnostics: no mesh bound");
+  sdm_status st = check_params(c, p);
+  if (st != SDM_OK) return st;
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  RunDesc r = make_desc(c, p, Q, ws);
+  Launch L = single(r);
+  if ((st = run(c, 0, L, s)) != SDM_OK) return st;
+  if ((st = run(c, 2, L, s)) != SDM_OK) return st;
+  hipLaunchKernelGGL(k_diag_reduce, dim3(1), dim3(256), 0, s, (const double*)r.Rp, r.E, out);
+  HIP_TRY(hipGetLastError());
+  return SDM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,298 @@
+"""Python binding of the gfx950 spectral-difference GLM-MHD library (libsdmhd.so).
+
+Argument marshalling only: every step of the residual and Runge-Kutta stage
+runs in the library's HIP kernels.  PyTorch provides device memory and streams.
+If the compiled library is missing this module raises at import time -- there
+is no CPU fallback.
+
+Entry points mirror include/sdmhd.h:
+  shell(Nz, Nr, p)/box(...)        host mesh, metrics and neighbour table
+  Solver(mesh, arith)              context + device copies of the mesh
+  Solver.residual(prm, Q)          R = dQ/dt                 (sdm_residual)
+  Solver.stage(prm, regs, st, dt)  one fused Shu-Osher stage (sdm_rk_stage)
+  Solver.step(prm, dt)             one SSPRK(5,3) step = five stages
+  Solver.diagnostics(prm, Q)       volume, mass, energy, KE, E_B, div B, ...
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsdmhd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2502_17805_amd/build.py "
+                      "(or __graft_entry__.build()) first -- there is no fallback path")
+
+_lib = C.CDLL(LIB_PATH)
+
+SDM_OK = 0
+
+
+class Params(C.Structure):
+    """Mirror of sdm_params."""
+    _fields_ = [(n, C.c_double) for n in ("gamma", "Rgas", "GM", "Omega", "nu", "kappa", "eta",
+                                          "kr_scale", "kr_c0", "kr_c1", "kr_c2", "kr_omega_per_r",
+                                          "c_h", "glm_a")] + [
+        ("powell", C.c_int32), ("wall_kind", C.c_int32 * 2), ("wall_mag", C.c_int32 * 2),
+        ("wall_th", C.c_int32 * 2), ("q_wall", C.c_double * 2), ("T_wall", C.c_double * 2),
+        ("ghost", C.c_void_p)]
+
+
+class Stage(C.Structure):
+    """Mirror of sdm_stage."""
+    _fields_ = [("n_in", C.c_int32), ("in_idx", C.c_int32 * 4), ("alpha", C.c_double * 4),
+                ("cur", C.c_int32), ("out", C.c_int32), ("beta", C.c_double),
+                ("traces_valid", C.c_int32)]
+
+
+class MeshDesc(C.Structure):
+    """Mirror of sdm_mesh."""
+    _fields_ = [("n_elem", C.c_int64), ("n_bfaces", C.c_int64), ("x_sp", C.c_void_p),
+                ("detJ", C.c_void_p), ("S_fp", C.c_void_p), ("nbr", C.c_void_p)]
+
+
+_vp, _i64p = C.c_void_p, C.POINTER(C.c_int64)
+_lib.sdm_last_error.restype = C.c_char_p
+_lib.sdm_version.restype = C.c_char_p
+_lib.sdm_shell_sizes.argtypes = [C.c_int, C.c_int, _i64p, _i64p]
+_lib.sdm_shell_build.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double] + [_vp] * 5
+_lib.sdm_box_sizes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _i64p, _i64p]
+_lib.sdm_box_build.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                               C.c_int, C.c_double, C.c_int] + [_vp] * 5
+_lib.sdm_tables.argtypes = [C.c_int] + [_vp] * 5
+_lib.sdm_create.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]
+_lib.sdm_destroy.argtypes = [_vp]
+_lib.sdm_mesh_bind.argtypes = [_vp, C.POINTER(MeshDesc)]
+_lib.sdm_workspace_size.argtypes = [_vp, C.POINTER(C.c_size_t)]
+_lib.sdm_residual.argtypes = [_vp, C.POINTER(Params), _vp, _vp, _vp, _vp]
+_lib.sdm_rk_stage.argtypes = [_vp, C.POINTER(Params), C.POINTER(C.c_void_p), C.c_int,
+                              C.POINTER(Stage), C.c_double, _vp, _vp]
+_lib.sdm_diagnostics.argtypes = [_vp, C.POINTER(Params), _vp, _vp, _vp, _vp]
+_lib.sdm_profile_enable.argtypes = [_vp, C.c_int]
+_lib.sdm_profile_read.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+for _f in ("sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes", "sdm_box_build", "sdm_tables",
+           "sdm_create", "sdm_destroy", "sdm_mesh_bind", "sdm_workspace_size", "sdm_residual",
+           "sdm_rk_stage", "sdm_diagnostics", "sdm_profile_enable", "sdm_profile_read"):
+    getattr(_lib, _f).restype = C.c_int
+
+EXPORTED = ("sdm_last_error", "sdm_version", "sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes",
+            "sdm_box_build", "sdm_tables", "sdm_create", "sdm_destroy", "sdm_mesh_bind",
+            "sdm_workspace_size", "sdm_residual", "sdm_rk_stage", "sdm_diagnostics",
+            "sdm_profile_enable", "sdm_profile_read")
+KERNELS = ("traces", "volume", "volume_diag", "finish_residual", "finish_stage")
+
+
+class SdmError(RuntimeError):
+    pass
+
+
+def _check(rc):
+    if rc != SDM_OK:
+        raise SdmError(f"status {rc}: {_lib.sdm_last_error().decode()}")
+
+
+def _p(a):
+    return C.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else C.c_void_p(a.data_ptr())
+
+
+def make_params(ghost=None, **kw) -> Params:
+    p = Params()
+    d = dict(gamma=5.0 / 3.0, Rgas=1.0, GM=0.0, Omega=0.0, nu=0.0, kappa=0.0, eta=0.0,
+             kr_scale=0.0, kr_c0=0.0, kr_c1=0.0, kr_c2=0.0, kr_omega_per_r=0.0, c_h=0.0, glm_a=0.0,
+             powell=0, wall_kind=(0, 0), wall_mag=(0, 0), wall_th=(0, 0), q_wall=(0.0, 0.0),
+             T_wall=(0.0, 0.0))
+    d.update(kw)
+    for k, v in d.items():
+        if k in ("wall_kind", "wall_mag", "wall_th"):
+            arr = getattr(p, k)
+            arr[0], arr[1] = int(v[0]), int(v[1])
+        elif k in ("q_wall", "T_wall"):
+            arr = getattr(p, k)
+            arr[0], arr[1] = float(v[0]), float(v[1])
+        elif k == "powell":
+            p.powell = int(v)
+        else:
+            setattr(p, k, float(v))
+    p.ghost = None if ghost is None else ghost.data_ptr()
+    return p
+
+
+@dataclasses.dataclass
+class Mesh:
+    """Host arrays of one mesh (layouts of include/sdmhd.h)."""
+    p: int
+    E: int
+    NB: int
+    x_sp: np.ndarray
+    detJ: np.ndarray
+    S_fp: np.ndarray
+    S_sp: np.ndarray
+    nbr: np.ndarray
+
+    @property
+    def N(self):
+        return self.p + 1
+
+
+def _alloc(p, E, NB):
+    N = p + 1
+    N3, NF = N ** 3, (N + 1) * N * N
+    return Mesh(p, E, NB, np.zeros((E, 3, N3)), np.zeros((E, N3)), np.zeros((E, 3, 3, NF)),
+                np.zeros((E, 3, 3, N3)), np.zeros((E, 6), dtype=np.int32))
+
+
+def shell(Nz: int, Nr: int, p: int, rb: float = 0.70, rt: float = 0.98) -> Mesh:
+    E, NB = C.c_int64(), C.c_int64()
+    _check(_lib.sdm_shell_sizes(Nz, Nr, C.byref(E), C.byref(NB)))
+    m = _alloc(p, E.value, NB.value)
+    _check(_lib.sdm_shell_build(Nz, Nr, p, rb, rt, _p(m.x_sp), _p(m.detJ), _p(m.S_fp), _p(m.S_sp),
+                                _p(m.nbr)))
+    return m
+
+
+def box(nx, ny, nz, p, L=(1.0, 1.0, 1.0), periodic=7, warp=0.0) -> Mesh:
+    E, NB = C.c_int64(), C.c_int64()
+    _check(_lib.sdm_box_sizes(nx, ny, nz, periodic, C.byref(E), C.byref(NB)))
+    m = _alloc(p, E.value, NB.value)
+    _check(_lib.sdm_box_build(nx, ny, nz, L[0], L[1], L[2], periodic, warp, p, _p(m.x_sp), _p(m.detJ),
+                              _p(m.S_fp), _p(m.S_sp), _p(m.nbr)))
+    return m
+
+
+def tables(p: int):
+    N = p + 1
+    xs, xf, I, D, W = np.zeros(N), np.zeros(N + 1), np.zeros((N + 1, N)), np.zeros((N, N + 1)), np.zeros(N)
+    _check(_lib.sdm_tables(p, _p(xs), _p(xf), _p(I), _p(D), _p(W)))
+    return xs, xf, I, D, W
+
+
+# Shu-Osher coefficients (alpha_ik, beta_ik) of the optimal five-stage,
+# third-order SSP Runge-Kutta scheme named by the paper (Sec. "Spectral
+# Difference Method"): published 14-digit values with the beta entries
+# corrected by a minimal-norm Newton step so that the third-order conditions
+# hold in double precision.
+SSP53_ALPHA = {(1, 0): 1.0, (2, 1): 1.0,
+               (3, 0): 0.56656131914032997754, (3, 2): 0.43343868085967002246,
+               (4, 0): 0.09299483444412999511, (4, 1): 0.000020903696200000000053,
+               (4, 3): 0.90698426185967000489,
+               (5, 0): 0.0073613226092000003456, (5, 1): 0.20127980325145000684,
+               (5, 2): 0.0018295538968200000286, (5, 4): 0.78952932024252999279}
+SSP53_BETA = {(1, 0): 0.37726891519897837344, (2, 1): 0.37726891516114840825,
+              (3, 2): 0.16352294101188272956, (4, 0): 0.00071997350394151505236,
+              (4, 3): 0.3421769684090429351, (5, 0): 0.0027771984070493497694,
+              (5, 1): 0.000015679038088402258468, (5, 4): 0.29786487003033598351}
+
+
+def ssp53_stages():
+    """The five stages on four registers A=u0, B=u1, C=u2, D=u3/u4 (out of
+    stage 5 -> A).  The stored residuals L(u0), L(u1) that stages 4 and 5
+    need are replaced by (u1 - u0)/(beta10 dt) and (u2 - u1)/(beta21 dt), so
+    each stage is one fused residual + linear combination."""
+    a, b = SSP53_ALPHA, SSP53_BETA
+    r0 = b[(4, 0)] / b[(1, 0)]
+    s0 = b[(5, 0)] / b[(1, 0)]
+    s1 = b[(5, 1)] / b[(2, 1)]
+    A, B, Cc, D = 0, 1, 2, 3
+    return [
+        (A, [(A, 1.0)], b[(1, 0)], B),
+        (B, [(B, 1.0)], b[(2, 1)], Cc),
+        (Cc, [(A, a[(3, 0)]), (Cc, a[(3, 2)])], b[(3, 2)], D),
+        (D, [(A, a[(4, 0)] - r0), (B, a[(4, 1)] + r0), (D, a[(4, 3)])], b[(4, 3)], D),
+        (D, [(A, a[(5, 0)] - s0), (B, a[(5, 1)] + s0 - s1), (Cc, a[(5, 2)] + s1), (D, a[(5, 4)])],
+         b[(5, 4)], A),
+    ]
+
+
+class Solver:
+    """A device context with one bound mesh, four FP64 state registers and
+    the workspace, all allocated through torch on the current device."""
+
+    def __init__(self, mesh: Mesh, arith: int = 0, device: int = 0):
+        import torch
+        self.torch = torch
+        self.mesh = mesh
+        self.dev = torch.device("cuda", device)
+        self.arith = arith
+        h = C.c_void_p()
+        _check(_lib.sdm_create(device, mesh.p, arith, C.byref(h)))
+        self._h = h
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(self.dev)  # noqa: E731
+        self.x_sp, self.detJ, self.S_fp, self.nbr = t(mesh.x_sp), t(mesh.detJ), t(mesh.S_fp), t(mesh.nbr)
+        md = MeshDesc(mesh.E, mesh.NB, self.x_sp.data_ptr(), self.detJ.data_ptr(), self.S_fp.data_ptr(),
+                      self.nbr.data_ptr())
+        _check(_lib.sdm_mesh_bind(h, C.byref(md)))
+        nb = C.c_size_t()
+        _check(_lib.sdm_workspace_size(h, C.byref(nb)))
+        self.ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.dev)
+        shp = (mesh.E, 9, mesh.N ** 3)
+        self.regs = [torch.zeros(shp, dtype=torch.float64, device=self.dev) for _ in range(4)]
+        self._traces_of = None  # register whose traces the workspace holds
+        self.diag_out = torch.zeros(16, dtype=torch.float64, device=self.dev)
+
+    def __del__(self):
+        try:
+            if self._h:
+                _lib.sdm_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.dev).cuda_stream)
+
+    def set_state(self, Q):
+        self.regs[0].copy_(self.torch.as_tensor(Q, dtype=self.torch.float64).to(self.dev))
+        self._traces_of = None
+
+    @property
+    def state(self):
+        return self.regs[0]
+
+    def residual(self, prm: Params, Q=None, out=None):
+        Q = self.regs[0] if Q is None else Q
+        R = self.torch.empty_like(Q) if out is None else out
+        _check(_lib.sdm_residual(self._h, C.byref(prm), Q.data_ptr(), R.data_ptr(), self.ws.data_ptr(),
+                                 self._stream()))
+        self._traces_of = None
+        return R
+
+    def stage(self, prm: Params, cur: int, inputs, beta: float, out: int, dt: float, regs=None):
+        regs = self.regs if regs is None else regs
+        st = Stage()
+        st.n_in = len(inputs)
+        for k, (idx, al) in enumerate(inputs):
+            st.in_idx[k] = idx
+            st.alpha[k] = al
+        st.cur, st.out, st.beta = cur, out, beta
+        st.traces_valid = 1 if (self._traces_of == cur and regs is self.regs) else 0
+        arr = (C.c_void_p * len(regs))(*[r.data_ptr() for r in regs])
+        _check(_lib.sdm_rk_stage(self._h, C.byref(prm), arr, len(regs), C.byref(st), dt, self.ws.data_ptr(),
+                                 self._stream()))
+        self._traces_of = out if regs is self.regs else None
+
+    def step(self, prm: Params, dt: float):
+        """One SSPRK(5,3) step of the state in register 0."""
+        for cur, inputs, beta, out in ssp53_stages():
+            self.stage(prm, cur, inputs, beta, out, dt)
+
+    def profile(self, enable: bool):
+        _check(_lib.sdm_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel: (total ms, launches)} of the launches since profile(True)."""
+        ms = (C.c_double * 8)()
+        cnt = (C.c_int64 * 8)()
+        _check(_lib.sdm_profile_read(self._h, ms, cnt))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNELS) if cnt[i]}
+
+    def diagnostics(self, prm: Params, Q=None):
+        Q = self.regs[0] if Q is None else Q
+        _check(_lib.sdm_diagnostics(self._h, C.byref(prm), Q.data_ptr(), self.diag_out.data_ptr(),
+                                    self.ws.data_ptr(), self._stream()))
+        self._traces_of = None
+        return self.diag_out.cpu().numpy()

@@ -1,0 +1,190 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Criterion (FP64): per variable v, max over points |R_gpu - R_oracle| <=
+TOL * T_v, where T_v is the oracle's round-off scale of the residual (sum of
+|terms| of the flux divergence over |J| plus |sources|).  An RK stage output u
+is compared with the scale max|u_v| + dt T_v (its two contributions: the
+register combination and dt times the residual).  TOL = 1e-12.
+"""
+import numpy as np
+import pytest
+
+from paper_2502_17805_amd import inputs as inp
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2502_17805_amd import sdmhd
+    return sdmhd
+
+
+def _run_params(bg, seed, **over):
+    pr = inp.run_params(seed, bg)
+    pr.update(over)
+    return pr
+
+
+def _both(sd, oracle, pr, ghost_np=None, solver=None):
+    import torch
+    g = None if ghost_np is None else torch.from_numpy(ghost_np).cuda()
+    return sd.make_params(ghost=g, **pr), oracle.make_params(**pr), g
+
+
+def _check_residual(sd, oracle, mesh_lib, mesh_ora, Q, pr, ghost=None, arith=0, tol=TOL):
+    import torch
+    s = sd.Solver(mesh_lib, arith=arith)
+    pg, po, g = _both(sd, oracle, pr, ghost)
+    Rg = s.residual(pg, torch.from_numpy(Q).cuda())
+    torch.cuda.synchronize()
+    Rg = Rg.cpu().numpy()
+    Ro, ts = mesh_ora.residual(po, Q, ghost, with_scale=True)
+    err = np.abs(Rg - Ro).max(axis=(0, 2))
+    assert np.isfinite(Rg).all()
+    assert (err <= tol * ts).all(), (err / ts)
+    return err / ts
+
+
+def _c1(sd, oracle, p=5, Nz=2, Nr=2, N_rho=3.0, seed=0):
+    ml = sd.shell(Nz, Nr, p)
+    mo = oracle.Mesh.shell(p + 1, Nz, Nr)
+    bg = inp.Background(N_rho)
+    Q = inp.shell_state(mo.get("x_sp"), bg, seed)
+    pr = _run_params(bg, seed)
+    ch = inp.glm_speed(Q)
+    pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
+    return ml, mo, bg, Q, pr
+
+
+def test_residual_c1_shell_p5(sd, oracle):
+    """48-element shell, p = 5, polytrope N_rho = 3 with seeded perturbations,
+    rotation, viscosity/conduction/resistivity, Powell and GLM terms,
+    conducting heat-flux inner wall and radial fixed-T outer wall."""
+    ml, mo, bg, Q, pr = _c1(sd, oracle)
+    _check_residual(sd, oracle, ml, mo, Q, pr)
+
+
+def test_residual_c1_shell_p3(sd, oracle):
+    ml, mo, bg, Q, pr = _c1(sd, oracle, p=3, Nz=3, Nr=2, N_rho=5.0, seed=3)
+    _check_residual(sd, oracle, ml, mo, Q, pr)
+
+
+def test_residual_far_from_equilibrium_normwise(sd, oracle):
+    """No cancellation: smooth random state, no gravity; the plain normwise
+    criterion |dR| <= 1e-12 max|R| holds per variable as well."""
+    import torch
+    ml = sd.shell(2, 2, 5)
+    mo = oracle.Mesh.shell(6, 2, 2)
+    Q = inp.smooth_random_state(mo.get("x_sp"), 21)
+    pr = dict(nu=2e-3, kappa=1e-3, eta=3e-3, c_h=2.0, glm_a=1.0, Omega=0.3, powell=1,
+              wall_mag=(1, 0), wall_th=(1, 0), q_wall=(0.0, 0.05), T_wall=(0.9, 1.1),
+              kr_scale=1e-3, kr_c0=1.0, kr_c1=-0.5, kr_c2=0.2, kr_omega_per_r=1.3)
+    s = sd.Solver(ml)
+    Rg = s.residual(sd.make_params(**pr), torch.from_numpy(Q).cuda()).cpu().numpy()
+    Ro, ts = mo.residual(oracle.make_params(**pr), Q, with_scale=True)
+    err = np.abs(Rg - Ro).max(axis=(0, 2))
+    assert (err <= TOL * ts).all(), err / ts
+    assert (err <= 1e-12 * np.abs(Ro).max(axis=(0, 2))).all(), err / np.abs(Ro).max(axis=(0, 2))
+
+
+def test_residual_dirichlet_warped_box_and_single_element(sd, oracle):
+    """All-Dirichlet warped box (ghost data on every boundary point), and the
+    degenerate single-element mesh whose six faces are all boundaries."""
+    for dims, per in (((3, 2, 4), 0), ((1, 1, 1), 0), ((3, 3, 2), 3)):
+        ml = sd.box(*dims, 5, L=(1.0, 0.9, 0.7), periodic=per, warp=0.01 if per == 0 else 0.0)
+        mo = oracle.Mesh.box(6, *dims, L=(1.0, 0.9, 0.7), periodic=per, warp=0.01 if per == 0 else 0.0)
+        Q = inp.smooth_random_state(mo.get("x_sp"), 5)
+        gh = inp.smooth_random_state(mo.get("x_bfp"), 5) if mo.NB else None
+        pr = dict(nu=1e-2, kappa=1e-2, eta=1e-2, c_h=1.5, glm_a=0.3, powell=1, wall_kind=(1, 1))
+        _check_residual(sd, oracle, ml, mo, Q, pr, ghost=gh)
+
+
+def test_ssprk53_steps_c1(sd, oracle):
+    """The C1 run: 10 SSPRK(5,3) steps on the 48-element shell; every step's
+    state against the oracle's."""
+    import torch
+    ml, mo, bg, Q, pr = _c1(sd, oracle)
+    dt = inp.time_step(Q, mo.get("S_sp"), mo.get("detJ_sp"), pr["c_h"], 0.1)
+    s = sd.Solver(ml)
+    pg, po, _ = _both(sd, oracle, pr)
+    s.set_state(Q)
+    qo = Q.copy()
+    for step in range(10):
+        _, ts = mo.residual(po, qo, with_scale=True)
+        s.step(pg, dt)
+        qo = mo.step(po, qo, dt)
+        qg = s.state.cpu().numpy()
+        scale = np.abs(qo).max(axis=(0, 2)) + dt * ts
+        err = np.abs(qg - qo).max(axis=(0, 2))
+        assert (err <= TOL * scale).all(), (step, err / scale)
+
+
+def test_single_stage_each_kind(sd, oracle):
+    """Each of the five fused stages separately (inputs from the oracle's own
+    Shu-Osher stages), so a wrong coefficient or register shows up alone."""
+    import torch
+    ml, mo, bg, Q, pr = _c1(sd, oracle)
+    dt = 0.01
+    a, b, c = oracle.ssprk53_table()
+    pg, po, _ = _both(sd, oracle, pr)
+    # oracle stage values u0..u5 and residuals
+    U, Lr = [Q], []
+    for i in range(1, 6):
+        Lr.append(mo.residual(po, U[i - 1]))
+        U.append(sum(a[i, k] * U[k] + dt * b[i, k] * Lr[k] for k in range(i)))
+    s = sd.Solver(ml)
+    stages = sd.ssp53_stages()
+    # register contents before stage i (A=u0, B=u1, C=u2, D=u3 or u4)
+    before = {0: (U[0], None, None, None), 1: (U[0], U[1], None, None), 2: (U[0], U[1], U[2], None),
+              3: (U[0], U[1], U[2], U[3]), 4: (U[0], U[1], U[2], U[4])}
+    for i, (cur, inputs, beta, out) in enumerate(stages):
+        _, ts = mo.residual(po, U[i], with_scale=True)
+        for r, val in enumerate(before[i]):
+            s.regs[r].copy_(torch.from_numpy(val if val is not None else np.zeros_like(Q)))
+        s._traces_of = None
+        s.stage(pg, cur, inputs, beta, out, dt)
+        got = s.regs[out].cpu().numpy()
+        want = U[i + 1]
+        scale = np.abs(want).max(axis=(0, 2)) + dt * ts
+        err = np.abs(got - want).max(axis=(0, 2))
+        assert (err <= TOL * scale).all(), (i, err / scale)
+
+
+def test_diagnostics_match(sd, oracle):
+    import torch
+    ml, mo, bg, Q, pr = _c1(sd, oracle)
+    s = sd.Solver(ml)
+    pg, po, _ = _both(sd, oracle, pr)
+    dg = s.diagnostics(pg, torch.from_numpy(Q).cuda())
+    do = mo.diagnostics(po, Q)
+    for k in (0, 1, 2, 3, 4, 6):
+        assert abs(dg[k] - do[k]) <= 1e-12 * abs(do[k]), (k, dg[k], do[k])
+    assert abs(dg[5] - do[5]) <= 1e-10 * do[5]
+    assert dg[7] == do[7] and dg[8] == do[8] == 0.0
+    Qn = Q.copy()
+    Qn[3, 4, 7] = np.nan
+    assert s.diagnostics(pg, torch.from_numpy(Qn).cuda())[8] == 1.0
+
+
+def test_deterministic_bitwise(sd, oracle):
+    import torch
+    ml, mo, bg, Q, pr = _c1(sd, oracle)
+    s = sd.Solver(ml)
+    pg, _, _ = _both(sd, oracle, pr)
+    r1 = s.residual(pg, torch.from_numpy(Q).cuda()).cpu().numpy()
+    r2 = s.residual(pg, torch.from_numpy(Q).cuda()).cpu().numpy()
+    assert np.array_equal(r1, r2)
+
+
+def test_mixed_precision_residual_bound(sd, oracle):
+    """FP32 residual arithmetic (FP64 state, metrics, RK): error against the
+    FP64 oracle stays within 1e-5 of the round-off scale per variable."""
+    ml, mo, bg, Q, pr = _c1(sd, oracle)
+    rel = _check_residual(sd, oracle, ml, mo, Q, pr, arith=1, tol=1e-5)
+    assert rel.max() > 1e-12  # really computed in FP32
