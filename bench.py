@@ -147,7 +147,7 @@ def main():
     pr = inp.run_params(seed, bg)
     ch = inp.glm_speed(Q)
     pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
-    dt = inp.time_step(Q, mesh.S_sp, mesh.detJ, ch, args.cfl)
+    dt = inp.time_step(Q, mesh.Sj_sp, ch, args.cfl)
     dof = mesh.E * N ** 3
     print(f"# mesh {args.config}: E={mesh.E} DOF={dof} host build {t_mesh:.1f}s dt={dt:.3e}", file=sys.stderr,
           flush=True)

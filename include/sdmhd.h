@@ -20,6 +20,8 @@
  *                       B_x, B_y, B_z, psi (FP64)
  *   x_sp   [E][3][N3]   physical solution-point coordinates (FP64)
  *   detJ   [E][N3]      Jacobian determinant at the solution points (FP64)
+ *   Sj_sp  [E][3 d][3 x][N3]  S^d_x / |J| at the solution points: the
+ *                       chain-rule factors d xi_d / d x (FP64)
  *   S_fp   [E][3 d][3 x][NF]  metric vector S^d = |J| grad(xi_d) at the
  *                       family-d flux points; family d stores its flux-point
  *                       index along axis d (d = 0: f + (N+1)(b + N c);
@@ -35,6 +37,10 @@
  *   increasing axis order; orientation o = 4 swap + 2 flip_b + flip_a maps
  *   it to the neighbour's point: (p, q) = swap ? (b, a) : (a, b);
  *   a' = flip_a ? N-1-p : p; b' = flip_b ? N-1-q : q.
+ *   n_face [E][6][3][N^2]  outward face normal at every face point: the
+ *                       symmetric (S_own - S_neighbour)/2 of the two sides'
+ *                       outward metric vectors (exact negatives across the
+ *                       face); S_own on boundary faces (FP64)
  *   ghost  [n_bfaces][9][N^2]  outside state on Dirichlet faces (device).
  *
  * Errors: every call returns an sdm_status; nothing is thrown across the
@@ -76,8 +82,8 @@ const char* sdm_version(void);
 sdm_status sdm_shell_sizes(int Nz, int Nr, int64_t* n_elem, int64_t* n_bfaces);
 
 /* Build the shell of degree p between radii rb < rt into caller HOST
- * buffers sized from sdm_shell_sizes (layouts above).  S_sp ([E][3][3][N3],
- * the metric vectors at the solution points) may be NULL.  Element index
+ * buffers sized from sdm_shell_sizes (layouts above); Sj_sp receives the
+ * chain-rule factors S^d/|J| at the solution points.  Element index
  * e = ((P Nr + k) Nz + j) Nz + i for cube patch P (+x,+y,-x,-y,+z,-z),
  * radial layer k (inner to outer), and equiangular indices (i, j).
  * The element map is the degree-N isoparametric interpolant of the exact
@@ -86,7 +92,8 @@ sdm_status sdm_shell_sizes(int Nz, int Nr, int64_t* n_elem, int64_t* n_bfaces);
  * Jacobi matrix J, transformed system Eq. "G.E. comp").  Uses all host
  * threads (OpenMP). */
 sdm_status sdm_shell_build(int Nz, int Nr, int p, double rb, double rt, double* x_sp,
-                           double* detJ, double* S_fp, double* S_sp, int32_t* nbr);
+                           double* detJ, double* S_fp, double* Sj_sp, int32_t* nbr,
+                           double* n_face);
 
 /* The same for an nx x ny x nz box [0,Lx]x[0,Ly]x[0,Lz] (element index
  * e = (k ny + j) nx + i), periodic in direction d if bit d of `periodic` is
@@ -98,7 +105,7 @@ sdm_status sdm_box_sizes(int nx, int ny, int nz, int periodic, int64_t* n_elem,
                          int64_t* n_bfaces);
 sdm_status sdm_box_build(int nx, int ny, int nz, double Lx, double Ly, double Lz,
                          int periodic, double warp, int p, double* x_sp, double* detJ,
-                         double* S_fp, double* S_sp, int32_t* nbr);
+                         double* S_fp, double* Sj_sp, int32_t* nbr, double* n_face);
 
 /* 1-D tables of the method for N = p+1 (host): solution points xs[N],
  * flux points xf[N+1], interpolation I[(N+1)][N] (SP basis at FPs),
@@ -121,7 +128,9 @@ typedef struct {
   const double* x_sp;
   const double* detJ;
   const double* S_fp;
+  const double* Sj_sp;
   const int32_t* nbr;
+  const double* n_face;
 } sdm_mesh;
 sdm_status sdm_mesh_bind(sdm_ctx* ctx, const sdm_mesh* mesh);
 
@@ -183,6 +192,35 @@ sdm_status sdm_rk_stage(sdm_ctx* ctx, const sdm_params* prm, double* const* regs
  * flag (1.0 if any), zeros after.  Deterministic (fixed reduction order). */
 sdm_status sdm_diagnostics(sdm_ctx* ctx, const sdm_params* prm, const double* Q, double* out,
                            void* ws, void* stream);
+
+/* ---------------- batched stages of independent runs ------------------ */
+
+/* One item of a batch: a run with its own context (bound mesh), parameters,
+ * registers and workspace, and the stage it takes next. */
+typedef struct {
+  sdm_ctx* ctx;
+  const sdm_params* prm;
+  double* const* regs;
+  int32_t n_regs;
+  sdm_stage stage;
+  double dt;
+  void* ws;
+} sdm_batch_item;
+
+/* Bytes of DEVICE scratch sdm_batch_stage needs for n_items runs (their
+ * descriptor tables). */
+sdm_status sdm_batch_workspace_size(int n_items, size_t* bytes);
+
+/* Serving: advance n_items independent runs by one fused RK stage each in
+ * shared launches (trace pass for items without valid traces, one volume
+ * pass, one finish pass), each a grid-stride loop over the concatenated
+ * elements of all runs with at most max_blocks workgroups (0: one per
+ * element).  Every run gets exactly the arithmetic of sdm_rk_stage on its
+ * own (results are bitwise identical alone and in a batch).  All items must
+ * share p, arithmetic and device.  The descriptor table is staged through
+ * library-owned pinned host memory and copied into batch_ws on `stream`. */
+sdm_status sdm_batch_stage(const sdm_batch_item* items, int n_items, void* batch_ws,
+                           size_t batch_ws_bytes, int max_blocks, void* stream);
 
 /* Per-kernel timing for benchmarks.  While enabled, every launch the
  * context makes is bracketed by two HIP events recorded on the call's

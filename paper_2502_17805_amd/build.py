@@ -20,7 +20,7 @@ def _run(cmd):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose=True) -> str:
+def build(verbose=True, defines=(), out=None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     host_o = os.path.join(BUILD, "sdm_host.o")
     kern_o = os.path.join(BUILD, "sdm_kernels.o")
@@ -28,11 +28,12 @@ def build(verbose=True) -> str:
           os.path.join(CSRC, "sdm_host.cpp"), "-o", host_o])
     _run(["hipcc", f"--offload-arch={ARCH}", "-std=c++17", "-O3", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-c", os.path.join(CSRC, "sdm_kernels.hip"), "-o", kern_o])
-    tmp = LIB + ".tmp"
+          *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, "sdm_kernels.hip"), "-o", kern_o])
+    lib = out or LIB
+    tmp = lib + ".tmp"
     _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, kern_o, host_o, "-lgomp"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -236,6 +236,10 @@ void element_geometry(const Tables1D& t, const Block3 X[3], double* x_sp, double
     const double g = J[2][0].v[q], h = J[2][1].v[q], k = J[2][2].v[q];
     detJ[q] = a * (e * k - f * h) - b * (d * k - f * g) + c * (d * h - e * g);
   }
+  // the chain-rule factors S^d/|J| at the solution points
+  if (S_sp)
+    for (int r = 0; r < 9; ++r)
+      for (int q = 0; q < N3; ++q) S_sp[r * N3 + q] /= detJ[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -351,6 +355,37 @@ inline double edge_tan(double s, int Nz) {
 // Public builders
 // ---------------------------------------------------------------------------
 
+// Symmetric outward normal at every element face point: n = (S_own - S_nbr)/2
+// with S_out = +-S^d at the face (sign by the face side); on boundary faces
+// n = S_own.  The two sides of an interior face get exact negatives.
+static void face_normals(int N, int64_t E, const double* S_fp, const int32_t* nbr, double* n_face) {
+  const int N2 = N * N, NF = (N + 1) * N2;
+  auto fp_of = [N](int d, int f, int a, int b) {
+    return d == 0 ? f + (N + 1) * (a + N * b) : (d == 1 ? a + N * (f + (N + 1) * b) : a + N * (b + N * f));
+  };
+  auto s_out = [&](int64_t e, int face, int a, int b, int c) {
+    const int d = face >> 1, side = face & 1;
+    const double v = S_fp[((e * 3 + d) * 3 + c) * NF + fp_of(d, side ? N : 0, a, b)];
+    return side ? v : -v;
+  };
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < E; ++e)
+    for (int f = 0; f < 6; ++f) {
+      const int32_t code = nbr[e * 6 + f];
+      for (int b = 0; b < N; ++b)
+        for (int a = 0; a < N; ++a)
+          for (int c = 0; c < 3; ++c) {
+            double v = s_out(e, f, a, b, c);
+            if (code >= 0) {
+              int a2, b2;
+              map_point(code & 7, N, a, b, a2, b2);
+              v = 0.5 * (v - s_out(code >> 6, (code >> 3) & 7, a2, b2, c));
+            }
+            n_face[((e * 6 + f) * 3 + c) * N2 + a + N * b] = v;
+          }
+    }
+}
+
 static int run_geometry(const Tables1D& t, int64_t E, const std::function<void(int64_t, Block3*)>& nodes,
                         double* x_sp, double* detJ, double* S_fp, double* S_sp) {
   const int N = t.N, NP = N + 1, N3 = N * N * N, NF = NP * N * N;
@@ -365,7 +400,7 @@ static int run_geometry(const Tables1D& t, int64_t E, const std::function<void(i
 }
 
 int shell_build(int Nz, int Nr, int p, double rb, double rt, double* x_sp, double* detJ,
-                double* S_fp, double* S_sp, int32_t* nbr) {
+                double* S_fp, double* S_sp, int32_t* nbr, double* n_face) {
   const Tables1D t = make_tables(p + 1);
   const int NP = p + 2;
   const int64_t E = 6LL * Nr * Nz * Nz;
@@ -405,11 +440,13 @@ int shell_build(int Nz, int Nr, int p, double rb, double rt, double* x_sp, doubl
       }
     }
   };
-  return run_geometry(t, E, nodes, x_sp, detJ, S_fp, S_sp);
+  run_geometry(t, E, nodes, x_sp, detJ, S_fp, S_sp);
+  if (n_face) face_normals(p + 1, E, S_fp, nbr, n_face);
+  return 0;
 }
 
 int box_build(int nx, int ny, int nz, double Lx, double Ly, double Lz, int periodic, double warp,
-              int p, double* x_sp, double* detJ, double* S_fp, double* S_sp, int32_t* nbr) {
+              int p, double* x_sp, double* detJ, double* S_fp, double* S_sp, int32_t* nbr, double* n_face) {
   const Tables1D t = make_tables(p + 1);
   const int NP = p + 2;
   const int n[3] = {nx, ny, nz};
@@ -441,7 +478,9 @@ int box_build(int nx, int ny, int nz, double Lx, double Ly, double Lz, int perio
           for (int d = 0; d < 3; ++d) X[d].at(a, b, c) = y[d] + s * L[d];
         }
   };
-  return run_geometry(t, E, nodes, x_sp, detJ, S_fp, S_sp);
+  run_geometry(t, E, nodes, x_sp, detJ, S_fp, S_sp);
+  if (n_face) face_normals(p + 1, E, S_fp, nbr, n_face);
+  return 0;
 }
 
 }  // namespace sdm

@@ -23,8 +23,8 @@ struct Tables1D {
 Tables1D make_tables(int N);
 
 int shell_build(int Nz, int Nr, int p, double rb, double rt, double* x_sp, double* detJ,
-                double* S_fp, double* S_sp, int32_t* nbr);
+                double* S_fp, double* S_sp, int32_t* nbr, double* n_face);
 int box_build(int nx, int ny, int nz, double Lx, double Ly, double Lz, int periodic, double warp,
-              int p, double* x_sp, double* detJ, double* S_fp, double* S_sp, int32_t* nbr);
+              int p, double* x_sp, double* detJ, double* S_fp, double* S_sp, int32_t* nbr, double* n_face);
 
 }  // namespace sdm

@@ -67,7 +67,9 @@ struct RunDesc {
   const double* x_sp;
   const double* detJ;
   const double* S_fp;
+  const double* Sj_sp;
   const int32_t* nbr;
+  const double* n_face;
   const double* ghost;
   const double* Q;     // state whose residual is taken
   void* Qtr;           // [E][6][9][N2]  T
@@ -110,6 +112,7 @@ template <typename T>
 __device__ __forceinline__ Phys<T> cvt_phys(const Phys<double>& p) {
   Phys<T> o;
   o.gm1 = (T)p.gm1; o.gamma = (T)p.gamma; o.Rgas = (T)p.Rgas; o.cp = (T)p.cp;
+  o.inv_R = (T)p.inv_R; o.inv_gamma = (T)p.inv_gamma;
   o.GM = (T)p.GM; o.Omega = (T)p.Omega; o.nu = (T)p.nu; o.kappa = (T)p.kappa; o.eta = (T)p.eta;
   o.kr_scale = (T)p.kr_scale; o.kr_c0 = (T)p.kr_c0; o.kr_c1 = (T)p.kr_c1; o.kr_c2 = (T)p.kr_c2;
   o.kr_w = (T)p.kr_w; o.c_h = (T)p.c_h; o.glm_a = (T)p.glm_a;
@@ -146,6 +149,80 @@ constexpr int block_threads() {
 }
 
 // ---------------------------------------------------------------------------
+// interpolation of one solution-point field along a line to one flux point
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__device__ __forceinline__ T line_interp(const T* f, const T* w, int s0, int st) {
+  T s = T(0);
+#pragma unroll
+  for (int i = 0; i < N; ++i) s += w[i] * f[s0 + i * st];
+  return s;
+}
+
+// Q and grad_x Q at one flux point: one pass over the line's N solution
+// points accumulating all 36 fields (bounded live state); optionally the
+// radiative diffusivity sampled at the SPs and interpolated the same way.
+template <int N, typename T>
+__device__ __forceinline__ T interp_point(const T* sQ, const T* sG, const T* w, int s0, int st, T qf[9],
+                                          T gf[27], bool use_kr, const RunDesc* rd, int64_t e,
+                                          const Phys<T>& P) {
+  constexpr int N3 = N * N * N;
+#pragma unroll
+  for (int v = 0; v < 9; ++v) qf[v] = T(0);
+#pragma unroll
+  for (int k = 0; k < 27; ++k) gf[k] = T(0);
+  T kf = T(0);
+#pragma unroll 1
+  for (int i = 0; i < N; ++i) {
+    const T wi = w[i];
+    const int sidx = s0 + i * st;
+#pragma unroll
+    for (int v = 0; v < 9; ++v) qf[v] += wi * sQ[v * N3 + sidx];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) gf[k] += wi * sG[k * N3 + sidx];
+    if (use_kr) {
+      const T x[3] = {(T)rd->x_sp[(e * 3 + 0) * N3 + sidx], (T)rd->x_sp[(e * 3 + 1) * N3 + sidx],
+                      (T)rd->x_sp[(e * 3 + 2) * N3 + sidx]};
+      kf += wi * kappa_r(x, P);
+    }
+  }
+  return kf;
+}
+
+// Outside state and outward normal at face point ab of face f: the
+// neighbour's stored trace (orientation-mapped), the ghost state on
+// Dirichlet faces; nothing on walls (their state is built from the own one).
+template <int N, typename T>
+__device__ __forceinline__ void load_outside(const RunDesc* rd, int64_t e, int f, int ab, int32_t code,
+                                             const T* Qtr, const Phys<T>& P, T q[9], T n[3]) {
+  constexpr int N2 = N * N;
+  const double* nf = rd->n_face + (e * 6 + f) * 3 * N2 + ab;
+  n[0] = (T)nf[0];
+  n[1] = (T)nf[N2];
+  n[2] = (T)nf[2 * N2];
+  if (code >= 0) {
+    const int64_t en = code >> 6;
+    const int fn = (code >> 3) & 7, o = code & 7;
+    int a2, b2;
+    omap<N>(o, ab % N, ab / N, a2, b2);
+    const T* tn = Qtr + (en * 6 + fn) * 9 * N2 + a2 + N * b2;
+#pragma unroll
+    for (int v = 0; v < 9; ++v) q[v] = tn[v * N2];
+  } else {
+    const int c2 = -code - 1, g = c2 & 3;
+    const int64_t bf = c2 >> 2;
+    if (g == 2 || wsel(g, P.wall_kind) == 1) {
+      const double* gh = rd->ghost + bf * 9 * N2 + ab;
+#pragma unroll
+      for (int v = 0; v < 9; ++v) q[v] = (T)gh[v * N2];
+    } else {
+#pragma unroll
+      for (int v = 0; v < 9; ++v) q[v] = T(0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // k_traces: face traces of Q (used before a run's first stage)
 // ---------------------------------------------------------------------------
 template <int N, typename T>
@@ -176,17 +253,37 @@ __global__ __launch_bounds__(block_threads<N>()) void k_traces(Launch L) {
 // ---------------------------------------------------------------------------
 // k_volume
 // ---------------------------------------------------------------------------
+// waves per SIMD the volume pass is compiled for (its register budget is
+// 512 / waves): FP64 keeps the whole budget, FP32 fits two waves
+#ifndef SDM_VOLUME_WAVES_F64
+#define SDM_VOLUME_WAVES_F64 1
+#endif
+#ifndef SDM_VOLUME_WAVES_F32
+#define SDM_VOLUME_WAVES_F32 2
+#endif
+template <typename T>
+constexpr int volume_waves() {
+  return sizeof(T) == 8 ? SDM_VOLUME_WAVES_F64 : SDM_VOLUME_WAVES_F32;
+}
+
 template <int N, typename T, bool DIAG>
-__global__ __launch_bounds__(block_threads<N>()) void k_volume(Launch L) {
+__global__ __launch_bounds__(block_threads<N>()) __attribute__((amdgpu_waves_per_eu(volume_waves<T>())))
+void k_volume(Launch L) {
   constexpr int N2 = N * N, N3 = N2 * N, NP = N + 1, NF = NP * N2, BS = block_threads<N>();
+  constexpr int NI = N2 * (N - 1);  // interior flux points of one family
   constexpr int UN = (9 * NF > 9 * 6 * N2) ? 9 * NF : 9 * 6 * N2;
+  // a thread keeps its own face point / interior flux points across phases
+  // when one pass covers them all
+  constexpr bool FACE_REG = 6 * N2 <= BS;
+  constexpr bool INT_REG = NI <= BS;
   __shared__ T sQ[9 * N3];
   __shared__ T sG[27 * N3];
-  __shared__ T sU[UN];  // common solution on the faces, then the family fluxes
+  __shared__ T sU[UN];  // face jumps (common value - own trace), then fluxes
   __shared__ double sRed[BS / 64][10];
   static_assert(BS >= N3, "one solution point per thread");
   const DevTab<T>& tb = tab<T>(N);
   const int tid = threadIdx.x;
+  const int ia0 = tid % N, ia1 = (tid / N) % N, ia2 = tid / N2;  // this thread's SP (tid < N3)
 
   for (int64_t w = blockIdx.x; w < L.n_work; w += gridDim.x) {
     const RunDesc* rd;
@@ -199,120 +296,142 @@ __global__ __launch_bounds__(block_threads<N>()) void k_volume(Launch L) {
     const T* Qtr = (const T*)rd->Qtr;
     const bool use_kr = P.kr_scale != T(0);
 
-    // A. state into LDS; 1/|J| of this thread's solution point
+    // A. every global read of this element is issued here: the state into
+    //    LDS; the chain-rule factors and position of this thread's SP; the
+    //    outside state and normal of this thread's face point; the metric at
+    //    this thread's interior flux points of the three families.
     for (int i = tid; i < 9 * N3; i += BS) sQ[i] = (T)Qe[i];
-    const T ji = tid < N3 ? T(1) / (T)rd->detJ[e * N3 + tid] : T(0);
-    __syncthreads();
-
-    // B. BR1 common solution at the 6 N^2 face points
-    for (int it = tid; it < 6 * N2; it += BS) {
-      const int f = it / N2, ab = it % N2, a = ab % N, b = ab / N;
-      const int d = f >> 1, fe = (f & 1) ? N : 0;
-      T qo[9], qc[9];
+    T ji = T(0), Sj[3][3], xs[3] = {T(0), T(0), T(0)};
+    if (tid < N3) {
+      ji = T(1) / (T)rd->detJ[e * N3 + tid];
 #pragma unroll
-      for (int v = 0; v < 9; ++v) {
-        T s = T(0);
+      for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int i = 0; i < N; ++i) s += tb.I[fe][i] * sQ[v * N3 + sp_line<N>(d, a, b, i)];
-        qo[v] = s;
+        for (int c = 0; c < 3; ++c) Sj[d][c] = (T)rd->Sj_sp[(e * 9 + d * 3 + c) * N3 + tid];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xs[c] = (T)rd->x_sp[(e * 3 + c) * N3 + tid];
+    }
+    T fq[9], fn[3];  // face point: outside state (neighbour trace or ghost), normal
+    int32_t fcode = 0;
+    if (FACE_REG && tid < 6 * N2) {
+      const int f = tid / N2, ab = tid % N2;
+      fcode = nb6[f];
+      load_outside<N>(rd, e, f, ab, fcode, Qtr, P, fq, fn);
+    }
+    T Sint[3][3];  // metric at the interior flux point `tid` of each family
+    if (!DIAG && INT_REG && tid < NI) {
+      const int line = tid / (N - 1), f = 1 + tid % (N - 1);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int fi = fp_fam<N>(d, f, line % N, line / N);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Sint[d][c] = (T)Se[(d * 3 + c) * NF + fi];
       }
-      const int32_t code = nb6[f];
-      if (code >= 0) {
-        const int64_t en = code >> 6;
-        const int fn = (code >> 3) & 7, o = code & 7;
-        int a2, b2;
-        omap<N>(o, a, b, a2, b2);
-        const T* tn = Qtr + (en * 6 + fn) * 9 * N2 + a2 + N * b2;
-#pragma unroll
-        for (int v = 0; v < 9; ++v) qc[v] = T(0.5) * (qo[v] + tn[v * N2]);
-      } else {
-        const int c2 = -code - 1, g = c2 & 3;
-        const int64_t bf = c2 >> 2;
-        if (g == 2 || P.wall_kind[g] == 1) {
-          const double* gh = rd->ghost + bf * 9 * N2 + ab;
-#pragma unroll
-          for (int v = 0; v < 9; ++v) qc[v] = T(0.5) * (qo[v] + (T)gh[v * N2]);
-        } else {
-          const int idx = fp_fam<N>(d, fe, a, b);
-          const T sg = (f & 1) ? T(1) : T(-1);
-          T n[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) n[c] = sg * (T)Se[(d * 3 + c) * NF + idx];
-          const T inn = T(1) / sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-          const T nh[3] = {n[0] * inn, n[1] * inn, n[2] * inn};
-          wall_common(qo, nh, g, P, qc);
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < 9; ++v) sU[(f * 9 + v) * N2 + ab] = qc[v];
     }
     __syncthreads();
 
-    // C. gradient at the solution points
-    for (int sp = tid; sp < N3; sp += BS) {
-      const int ia[3] = {sp % N, (sp / N) % N, sp / N2};
-      T Sj[3][3];
+    // B. BR1 common solution at the 6 N^2 face points, stored as the jump
+    //    (common value - own trace) that the gradient correction uses.
+    //    B1: own traces into the (still unused) gradient buffer sG.
+    T* sTr = sG;  // [6][9][N2]
+    for (int it = tid; it < 6 * 9 * N2; it += BS) {
+      const int ab = it % N2, fv = it / N2, v = fv % 9, f = fv / 9;
+      const int d = f >> 1;
+      const int st = d == 0 ? 1 : (d == 1 ? N : N2);
+      sTr[it] = line_interp<N>(sQ + v * N3, tb.I[(f & 1) ? N : 0], sp_line<N>(d, ab % N, ab / N, 0), st);
+    }
+    __syncthreads();
+    //    B2: jumps from the own and the outside (neighbour, wall or ghost) state
+    for (int it = tid; it < 6 * N2; it += BS) {
+      const int f = it / N2, ab = it % N2;
+      T q_out[9], n[3];
+      int32_t code;
+      if (FACE_REG) {
+        code = fcode;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int p = d == 0 ? ia[1] : ia[0], q = d == 2 ? ia[1] : ia[2], i = ia[d];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          T s = T(0);
-#pragma unroll
-          for (int f = 0; f < NP; ++f) s += tb.L[i][f] * (T)Se[(d * 3 + c) * NF + fp_fam<N>(d, f, p, q)];
-          Sj[d][c] = s * ji;
-        }
+        for (int v = 0; v < 9; ++v) q_out[v] = fq[v];
+        n[0] = fn[0]; n[1] = fn[1]; n[2] = fn[2];
+      } else {
+        code = nb6[f];
+        load_outside<N>(rd, e, f, ab, code, Qtr, P, q_out, n);
       }
-      T g27[27];
+      const T* own = sTr + f * 9 * N2 + ab;
+      T* dst = sU + f * 9 * N2 + ab;
+      const int g = code >= 0 ? -1 : ((-code - 1) & 3);
+      if (code >= 0 || g == 2 || wsel(g, P.wall_kind) == 1) {
 #pragma unroll
-      for (int k = 0; k < 27; ++k) g27[k] = T(0);
+        for (int v = 0; v < 9; ++v) dst[v * N2] = T(0.5) * (q_out[v] - own[v * N2]);
+      } else {
+        T qo[9], qc[9];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int p = d == 0 ? ia[1] : ia[0], q = d == 2 ? ia[1] : ia[2], i = ia[d];
-        const int pq = p + N * q;
+        for (int v = 0; v < 9; ++v) qo[v] = own[v * N2];
+        const T inn = T(1) / sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        const T nh[3] = {n[0] * inn, n[1] * inn, n[2] * inn};
+        wall_common(qo, nh, g, P, qc);
 #pragma unroll
-        for (int v = 0; v < 9; ++v) {
-          T der = T(0), t0 = T(0), tN = T(0);
-#pragma unroll
-          for (int j = 0; j < N; ++j) {
-            const T qv = sQ[v * N3 + sp_line<N>(d, p, q, j)];
-            der += tb.DI[i][j] * qv;
-            t0 += tb.I[0][j] * qv;
-            tN += tb.I[N][j] * qv;
-          }
-          der += tb.D[i][0] * (sU[((2 * d) * 9 + v) * N2 + pq] - t0) +
-                 tb.D[i][N] * (sU[((2 * d + 1) * 9 + v) * N2 + pq] - tN);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) g27[v * 3 + c] += Sj[d][c] * der;
-        }
+        for (int v = 0; v < 9; ++v) dst[v * N2] = qc[v] - qo[v];
       }
+    }
+    __syncthreads();
+
+    // C. gradient at the solution points.
+    //    C1: derivative of each variable along each line: the solution
+    //    polynomial's own derivative plus the lifting of the two end jumps;
+    //    one (direction, line, variable) per thread, point index uniform so
+    //    the table entries are scalar loads.  Written to sG as dQ/dxi_d.
+    for (int it = tid; it < 3 * 9 * N2; it += BS) {
+      const int pq = it % N2, dv = it / N2, v = dv % 9, d = dv / 9;
+      const int st = d == 0 ? 1 : (d == 1 ? N : N2);
+      const int s0 = sp_line<N>(d, pq % N, pq / N, 0);
+      T ln[N];
 #pragma unroll
-      for (int k = 0; k < 27; ++k) sG[k * N3 + sp] = g27[k];
+      for (int j = 0; j < N; ++j) ln[j] = sQ[v * N3 + s0 + j * st];
+      const T j0 = sU[((2 * d) * 9 + v) * N2 + pq], jN = sU[((2 * d + 1) * 9 + v) * N2 + pq];
+      T* out = sG + (v * 3 + d) * N3 + s0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        T dd = tb.D[i][0] * j0 + tb.D[i][N] * jN;
+#pragma unroll
+        for (int j = 0; j < N; ++j) dd += tb.DI[i][j] * ln[j];
+        out[i * st] = dd;
+      }
+    }
+    __syncthreads();
+    //    C2: chain rule to physical space, grad_x Q = sum_d (S^d/|J|) dQ/dxi_d,
+    //    in place, one solution point per thread
+    if (tid < N3) {
+#pragma unroll
+      for (int v = 0; v < 9; ++v) {
+        T* g = sG + v * 3 * N3 + tid;
+        const T d0 = g[0], d1 = g[N3], d2 = g[2 * N3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g[c * N3] = Sj[0][c] * d0 + Sj[1][c] * d1 + Sj[2][c] * d2;
+      }
     }
     __syncthreads();
 
     if (DIAG) {
       // per-element diagnostics: W^3 |J|-weighted sums, maxima, NaN flag
       double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-      for (int sp = tid; sp < N3; sp += BS) {
-        const int a = sp % N, b = (sp / N) % N, c = sp / N2;
-        const double wq = (double)tb.W[a] * (double)tb.W[b] * (double)tb.W[c] * rd->detJ[e * N3 + sp];
+      if (tid < N3) {
+        const int sp = tid;
+        const double wq = (double)tb.W[ia0] * (double)tb.W[ia1] * (double)tb.W[ia2] * rd->detJ[e * N3 + sp];
         const double* q = Qe + sp;
         const double rho = q[0];
         const double m2 = q[N3] * q[N3] + q[2 * N3] * q[2 * N3] + q[3 * N3] * q[3 * N3];
         const double b2 = q[5 * N3] * q[5 * N3] + q[6 * N3] * q[6 * N3] + q[7 * N3] * q[7 * N3];
         const double db = (double)sG[15 * N3 + sp] + (double)sG[19 * N3 + sp] + (double)sG[23 * N3 + sp];
-        acc[0] += wq;
-        acc[1] += wq * rho;
-        acc[2] += wq * q[4 * N3];
-        acc[3] += wq * 0.5 * m2 / rho;
-        acc[4] += wq * 0.5 * b2;
-        acc[5] = fmax(acc[5], fabs(db));
-        acc[6] += wq * db * db;
-        acc[7] = fmax(acc[7], fabs(q[8 * N3]));
+        acc[0] = wq;
+        acc[1] = wq * rho;
+        acc[2] = wq * q[4 * N3];
+        acc[3] = wq * 0.5 * m2 / rho;
+        acc[4] = wq * 0.5 * b2;
+        acc[5] = fabs(db);
+        acc[6] = wq * db * db;
+        acc[7] = fabs(q[8 * N3]);
         bool bad = false;
         for (int v = 0; v < 9; ++v) bad = bad || !isfinite(q[v * N3]);
-        acc[8] = bad ? 1.0 : acc[8];
+        acc[8] = bad ? 1.0 : 0.0;
       }
       // wave reduction in a fixed order, then across waves
       for (int k = 0; k < 9; ++k) {
@@ -336,138 +455,142 @@ __global__ __launch_bounds__(block_threads<N>()) void k_volume(Launch L) {
       continue;
     }
 
-    // D. per family: fluxes at the flux points, then the divergence
+    // D. fluxes and their divergence.
+    //    D1: the 6 N^2 face points (common fluxes); D2: their lifting into the
+    //    divergence; then per family d: D3 the interior flux points and D4
+    //    their contribution to the divergence.  sU is reused by each pass.
     T div[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v) div[v] = T(0);
     T* Vtr = (T*)rd->Vtr;
 #pragma unroll 1
+    for (int it = tid; it < 6 * N2; it += BS) {
+      const int face = it / N2, ab = it % N2, p = ab % N, q = ab / N;
+      const int d = face >> 1, fe = (face & 1) ? N : 0;
+      const int st = d == 0 ? 1 : (d == 1 ? N : N2);
+      const int s0 = sp_line<N>(d, p, q, 0);
+      T qf[9], gf[27];
+      T kf = interp_point<N>(sQ, sG, tb.I[fe], s0, st, qf, gf, use_kr, rd, e, P);
+      T qx[9], n[3];
+      int32_t code;
+      if (FACE_REG) {
+        code = fcode;
+#pragma unroll
+        for (int v = 0; v < 9; ++v) qx[v] = fq[v];
+        n[0] = fn[0]; n[1] = fn[1]; n[2] = fn[2];
+      } else {
+        code = nb6[face];
+        load_outside<N>(rd, e, face, ab, code, Qtr, P, qx, n);
+      }
+      T F[9];
+      ViscLocal<T> vl;
+      const int g = code >= 0 ? -1 : ((-code - 1) & 3);
+      if (code >= 0) {
+        // interior face: Rusanov on the symmetric normal, own half of BR1 viscous
+        viscous_local(qf, gf, kf, P, vl);
+        T Fv[7];
+        flux_viscous7(vl, n, P, Fv);
+        T* vt = Vtr + (e * 6 + face) * 7 * N2 + ab;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) vt[c * N2] = Fv[c];
+        rusanov(qf, qx, n, P, F);
+#pragma unroll
+        for (int c = 0; c < 7; ++c) F[1 + c] -= T(0.5) * Fv[c];
+      } else if (g == 2 || wsel(g, P.wall_kind) == 1) {
+        // Dirichlet: Rusanov with the ghost state, BR1 average of the viscous
+        // fluxes of both states with the interior gradient
+        rusanov(qf, qx, n, P, F);
+        T Fv[7];
+        viscous_local(qf, gf, kf, P, vl);
+        flux_viscous7(vl, n, P, Fv);
+#pragma unroll
+        for (int c = 0; c < 7; ++c) F[1 + c] -= T(0.5) * Fv[c];
+        viscous_local(qx, gf, kf, P, vl);
+        flux_viscous7(vl, n, P, Fv);
+#pragma unroll
+        for (int c = 0; c < 7; ++c) F[1 + c] -= T(0.5) * Fv[c];
+      } else {
+        // physical wall
+        const T nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        const T inn = T(1) / nn;
+        const T nh[3] = {n[0] * inn, n[1] * inn, n[2] * inn};
+        wall_mirror(qf, nh, g, P, qx);
+        rusanov(qf, qx, n, P, F);
+        wall_common(qf, nh, g, P, qx);
+        viscous_local(qx, gf, kf, P, vl);
+        wall_viscous_sub(vl, n, nh, nn, g, P, F);
+      }
+      // the flux polynomial of family d takes -F at its coordinate 0, +F at 1
+      const T sg = (face & 1) ? T(1) : T(-1);
+#pragma unroll
+      for (int v = 0; v < 9; ++v) sU[(face * 9 + v) * N2 + ab] = sg * F[v];
+    }
+    __syncthreads();
+    if (tid < N3) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int p = d == 0 ? ia1 : ia0, q = d == 2 ? ia1 : ia2, i = d == 0 ? ia0 : (d == 1 ? ia1 : ia2);
+        const int pq = p + N * q;
+        const T d0 = tb.D[i][0], dN = tb.D[i][N];
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+          div[v] += d0 * sU[((2 * d) * 9 + v) * N2 + pq] + dN * sU[((2 * d + 1) * 9 + v) * N2 + pq];
+      }
+    }
+    __syncthreads();
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-      for (int it = tid; it < NF; it += BS) {
-        const int f = it % NP, line = it / NP, p = line % N, q = line / N;
+      const int st = d == 0 ? 1 : (d == 1 ? N : N2);
+#pragma unroll 1
+      for (int it = tid; it < NI; it += BS) {
+        const int line = it / (N - 1), f = 1 + it % (N - 1);
+        const int p = line % N, q = line / N;
+        const int s0 = sp_line<N>(d, p, q, 0);
         T qf[9], gf[27];
-        T kf = T(0);
-#pragma unroll
-        for (int v = 0; v < 9; ++v) qf[v] = T(0);
-#pragma unroll
-        for (int k = 0; k < 27; ++k) gf[k] = T(0);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          const T w = tb.I[f][i];
-          const int s = sp_line<N>(d, p, q, i);
-#pragma unroll
-          for (int v = 0; v < 9; ++v) qf[v] += w * sQ[v * N3 + s];
-#pragma unroll
-          for (int k = 0; k < 27; ++k) gf[k] += w * sG[k * N3 + s];
-        }
-        if (use_kr) {  // radiative diffusivity sampled at the SPs, interpolated like Q
-          for (int i = 0; i < N; ++i) {
-            const int s = sp_line<N>(d, p, q, i);
-            const T x[3] = {(T)rd->x_sp[(e * 3 + 0) * N3 + s], (T)rd->x_sp[(e * 3 + 1) * N3 + s],
-                            (T)rd->x_sp[(e * 3 + 2) * N3 + s]};
-            kf += tb.I[f][i] * kappa_r(x, P);
-          }
-        }
-        const int fi = fp_fam<N>(d, f, p, q);
+        T kf = interp_point<N>(sQ, sG, tb.I[f], s0, st, qf, gf, use_kr, rd, e, P);
         T Sd[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Sd[c] = (T)Se[(d * 3 + c) * NF + fi];
-        T F[9];
-        if (f != 0 && f != N) {
-          T Fv[7];
-          ViscLocal<T> vl;
-          viscous_local(qf, gf, kf, P, vl);
-          flux_inviscid(qf, Sd, P, F);
-          flux_viscous7(vl, Sd, P, Fv);
-#pragma unroll
-          for (int c = 0; c < 7; ++c) F[1 + c] -= Fv[c];
+        if (INT_REG) {
+          Sd[0] = Sint[d][0]; Sd[1] = Sint[d][1]; Sd[2] = Sint[d][2];
         } else {
-          const int face = 2 * d + (f == N ? 1 : 0);
-          const T sg = f == N ? T(1) : T(-1);
-          const T no[3] = {sg * Sd[0], sg * Sd[1], sg * Sd[2]};
-          const int32_t code = nb6[face];
-          if (code >= 0) {
-            const int64_t en = code >> 6;
-            const int fn = (code >> 3) & 7, o = code & 7;
-            int a2, b2;
-            omap<N>(o, p, q, a2, b2);
-            const T* tn = Qtr + (en * 6 + fn) * 9 * N2 + a2 + N * b2;
-            T qn[9];
+          const int fi = fp_fam<N>(d, f, p, q);
 #pragma unroll
-            for (int v = 0; v < 9; ++v) qn[v] = tn[v * N2];
-            const int dn = fn >> 1;
-            const int fin = fp_fam<N>(dn, (fn & 1) ? N : 0, a2, b2);
-            const T sgn = (fn & 1) ? T(1) : T(-1);
-            const double* Sen = rd->S_fp + en * 9 * NF;
-            T n[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) n[c] = T(0.5) * (no[c] - sgn * (T)Sen[(dn * 3 + c) * NF + fin]);
-            rusanov(qf, qn, n, P, F);
-            T Fv[7];
-            ViscLocal<T> vl;
-            viscous_local(qf, gf, kf, P, vl);
-            flux_viscous7(vl, n, P, Fv);
-            T* vt = Vtr + (e * 6 + face) * 7 * N2 + p + N * q;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) {
-              vt[c * N2] = Fv[c];
-              F[1 + c] -= T(0.5) * Fv[c];
-            }
-          } else {
-            const int c2 = -code - 1, g = c2 & 3;
-            const int64_t bf = c2 >> 2;
-            if (g == 2 || P.wall_kind[g] == 1) {
-              const double* gh = rd->ghost + bf * 9 * N2 + p + N * q;
-              T qg[9];
-#pragma unroll
-              for (int v = 0; v < 9; ++v) qg[v] = (T)gh[v * N2];
-              rusanov(qf, qg, no, P, F);
-              T Fv1[7], Fv2[7];
-              ViscLocal<T> vl;
-              viscous_local(qf, gf, kf, P, vl);
-              flux_viscous7(vl, no, P, Fv1);
-              viscous_local(qg, gf, kf, P, vl);
-              flux_viscous7(vl, no, P, Fv2);
-#pragma unroll
-              for (int c = 0; c < 7; ++c) F[1 + c] -= T(0.5) * (Fv1[c] + Fv2[c]);
-            } else {
-              wall_flux(qf, gf, kf, no, g, P, F);
-            }
-          }
-#pragma unroll
-          for (int v = 0; v < 9; ++v) F[v] *= sg;
+          for (int c = 0; c < 3; ++c) Sd[c] = (T)Se[(d * 3 + c) * NF + fi];
         }
+        ViscLocal<T> vl;
+        viscous_local(qf, gf, kf, P, vl);
+        T Fv[7], F[9];
+        flux_viscous7(vl, Sd, P, Fv);
+        flux_inviscid(qf, Sd, P, F);
 #pragma unroll
-        for (int v = 0; v < 9; ++v) sU[v * NF + it] = F[v];
+        for (int c = 0; c < 7; ++c) F[1 + c] -= Fv[c];
+#pragma unroll
+        for (int v = 0; v < 9; ++v) sU[v * NI + it] = F[v];
       }
       __syncthreads();
-      for (int sp = tid; sp < N3; sp += BS) {
-        const int ia[3] = {sp % N, (sp / N) % N, sp / N2};
-        const int p = d == 0 ? ia[1] : ia[0], q = d == 2 ? ia[1] : ia[2], i = ia[d];
-        const int base = (p + N * q) * NP;
+      if (tid < N3) {
+        const int p = d == 0 ? ia1 : ia0, q = d == 2 ? ia1 : ia2, i = d == 0 ? ia0 : (d == 1 ? ia1 : ia2);
+        const int base = (p + N * q) * (N - 1);
+#pragma unroll 1
+        for (int f = 1; f < N; ++f) {
+          const T df = tb.D[i][f];
 #pragma unroll
-        for (int v = 0; v < 9; ++v) {
-          T s = T(0);
-#pragma unroll
-          for (int f = 0; f < NP; ++f) s += tb.D[i][f] * sU[v * NF + base + f];
-          div[v] += s;  // BS >= N3: each thread owns at most one solution point
+          for (int v = 0; v < 9; ++v) div[v] += df * sU[v * NI + base + f - 1];
         }
       }
       __syncthreads();
     }
 
     // E. sources (Eq. "M") and the partial residual -div/|J| + M
-    for (int sp = tid; sp < N3; sp += BS) {
+    if (tid < N3) {
+      const int sp = tid;
       T q[9];
 #pragma unroll
       for (int v = 0; v < 9; ++v) q[v] = sQ[v * N3 + sp];
-      const T x[3] = {(T)rd->x_sp[(e * 3 + 0) * N3 + sp], (T)rd->x_sp[(e * 3 + 1) * N3 + sp],
-                      (T)rd->x_sp[(e * 3 + 2) * N3 + sp]};
       T gv[3] = {T(0), T(0), T(0)};
       if (P.GM != T(0)) {
-        const T r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-        const T s = -P.GM / (r2 * sqrt(r2));
-        gv[0] = s * x[0]; gv[1] = s * x[1]; gv[2] = s * x[2];
+        const T r2 = xs[0] * xs[0] + xs[1] * xs[1] + xs[2] * xs[2];
+        const T sc = -P.GM / (r2 * sqrt(r2));
+        gv[0] = sc * xs[0]; gv[1] = sc * xs[1]; gv[2] = sc * xs[2];
       }
       const T ir = T(1) / q[0];
       const T db = P.powell ? sG[15 * N3 + sp] + sG[19 * N3 + sp] + sG[23 * N3 + sp] : T(0);
@@ -678,6 +801,8 @@ Phys<double> to_phys(const sdm_params* p) {
   o.gm1 = p->gamma - 1.0;
   o.Rgas = p->Rgas;
   o.cp = p->gamma * p->Rgas / (p->gamma - 1.0);
+  o.inv_R = 1.0 / p->Rgas;
+  o.inv_gamma = 1.0 / p->gamma;
   o.GM = p->GM; o.Omega = p->Omega; o.nu = p->nu; o.kappa = p->kappa; o.eta = p->eta;
   o.kr_scale = p->kr_scale; o.kr_c0 = p->kr_c0; o.kr_c1 = p->kr_c1; o.kr_c2 = p->kr_c2;
   o.kr_w = p->kr_omega_per_r;
@@ -754,7 +879,9 @@ RunDesc make_desc(const sdm_ctx* c, const sdm_params* p, const double* Q, void* 
   r.x_sp = c->mesh.x_sp;
   r.detJ = c->mesh.detJ;
   r.S_fp = c->mesh.S_fp;
+  r.Sj_sp = c->mesh.Sj_sp;
   r.nbr = c->mesh.nbr;
+  r.n_face = c->mesh.n_face;
   r.ghost = p ? p->ghost : nullptr;
   r.Q = Q;
   r.Qtr = (char*)ws + off[0];
@@ -765,9 +892,9 @@ RunDesc make_desc(const sdm_ctx* c, const sdm_params* p, const double* Q, void* 
 }
 
 template <int N, typename T>
-hipError_t launch_all(int which, const Launch& L, hipStream_t s) {
+hipError_t launch_all(int which, const Launch& L, hipStream_t s, int64_t cap) {
   constexpr int BS = block_threads<N>();
-  const unsigned grid = (unsigned)std::min<int64_t>(L.n_work, (int64_t)1 << 30);
+  const unsigned grid = (unsigned)std::min<int64_t>(std::min<int64_t>(L.n_work, cap), (int64_t)1 << 30);
   if (L.n_work == 0) return hipSuccess;
   switch (which) {
     case 0: hipLaunchKernelGGL((k_traces<N, T>), dim3(grid), dim3(BS), 0, s, L); break;
@@ -781,19 +908,27 @@ hipError_t launch_all(int which, const Launch& L, hipStream_t s) {
 }
 
 template <typename T>
+hipError_t dispatch_N(int N, int which, const Launch& L, hipStream_t s, int64_t cap);
+template <typename T>
 hipError_t dispatch_N(int N, int which, const Launch& L, hipStream_t s) {
+  return dispatch_N<T>(N, which, L, s, (int64_t)1 << 30);
+}
+template <typename T>
+hipError_t dispatch_N(int N, int which, const Launch& L, hipStream_t s, int64_t cap) {
   switch (N) {
-    case 2: return launch_all<2, T>(which, L, s);
-    case 3: return launch_all<3, T>(which, L, s);
-    case 4: return launch_all<4, T>(which, L, s);
-    case 5: return launch_all<5, T>(which, L, s);
-    case 6: return launch_all<6, T>(which, L, s);
-    case 7: return launch_all<7, T>(which, L, s);
+    case 2: return launch_all<2, T>(which, L, s, cap);
+    case 3: return launch_all<3, T>(which, L, s, cap);
+    case 4: return launch_all<4, T>(which, L, s, cap);
+    case 5: return launch_all<5, T>(which, L, s, cap);
+    case 6: return launch_all<6, T>(which, L, s, cap);
+    case 7: return launch_all<7, T>(which, L, s, cap);
     default: return hipErrorInvalidValue;
   }
 }
 
-sdm_status run(sdm_ctx* c, int which, const Launch& L, hipStream_t s) {
+sdm_status run_capped(sdm_ctx* c, int which, const Launch& L, hipStream_t s, int64_t cap);
+sdm_status run(sdm_ctx* c, int which, const Launch& L, hipStream_t s) { return run_capped(c, which, L, s, (int64_t)1 << 30); }
+sdm_status run_capped(sdm_ctx* c, int which, const Launch& L, hipStream_t s, int64_t cap) {
   size_t e0 = 0;
   if (c->prof) {
     while (c->ev.size() < c->ev_used + 2) {
@@ -805,7 +940,7 @@ sdm_status run(sdm_ctx* c, int which, const Launch& L, hipStream_t s) {
     c->ev_used += 2;
     HIP_TRY(hipEventRecord(c->ev[e0], s));
   }
-  hipError_t e = c->arith ? dispatch_N<float>(c->N, which, L, s) : dispatch_N<double>(c->N, which, L, s);
+  hipError_t e = c->arith ? dispatch_N<float>(c->N, which, L, s, cap) : dispatch_N<double>(c->N, which, L, s, cap);
   if (e != hipSuccess) return fail(SDM_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
   if (c->prof) {
     HIP_TRY(hipEventRecord(c->ev[e0 + 1], s));
@@ -827,6 +962,50 @@ Launch single(const RunDesc& r) {
 
 }  // namespace
 
+namespace {
+
+// Pinned host staging for batch descriptor tables: a small ring of buffers,
+// each reused only after the copy that last read it has completed.
+struct Staging {
+  std::mutex mu;
+  struct Slot {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+  };
+  Slot slot[8];
+  int next = 0;
+};
+Staging g_stage;
+
+sdm_status stage_copy(const void* src, size_t bytes, void* dst_dev, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_stage.mu);
+  Staging::Slot& sl = g_stage.slot[g_stage.next];
+  g_stage.next = (g_stage.next + 1) % 8;
+  if (sl.pending) {
+    HIP_TRY(hipEventSynchronize(sl.done));
+    sl.pending = false;
+  }
+  if (sl.cap < bytes) {
+    if (sl.host) HIP_TRY(hipHostFree(sl.host));
+    sl.host = nullptr;
+    sl.cap = 0;
+    HIP_TRY(hipHostMalloc(&sl.host, bytes, hipHostMallocDefault));
+    sl.cap = bytes;
+  }
+  if (!sl.done) HIP_TRY(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+  std::memcpy(sl.host, src, bytes);
+  HIP_TRY(hipMemcpyAsync(dst_dev, sl.host, bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(sl.done, s));
+  sl.pending = true;
+  return SDM_OK;
+}
+
+size_t batch_table_bytes(int n) { return align256(sizeof(RunDesc) * (size_t)n) + align256(sizeof(int64_t) * (n + 1)); }
+
+}  // namespace
+
 extern "C" {
 
 const char* sdm_last_error(void) { return g_err.c_str(); }
@@ -841,11 +1020,12 @@ sdm_status sdm_shell_sizes(int Nz, int Nr, int64_t* n_elem, int64_t* n_bfaces) {
 }
 
 sdm_status sdm_shell_build(int Nz, int Nr, int p, double rb, double rt, double* x_sp, double* detJ,
-                           double* S_fp, double* S_sp, int32_t* nbr) {
+                           double* S_fp, double* Sj_sp, int32_t* nbr, double* n_face) {
   if (Nz < 1 || Nr < 1 || p < 1 || p > kNMax - 1 || !(rb > 0) || !(rt > rb))
     return fail(SDM_EINVAL, "shell build: need Nz, Nr >= 1, 1 <= p <= 7, 0 < rb < rt");
-  if (!x_sp || !detJ || !S_fp || !nbr) return fail(SDM_EINVAL, "shell build: NULL output");
-  if (shell_build(Nz, Nr, p, rb, rt, x_sp, detJ, S_fp, S_sp, nbr)) return fail(SDM_EINVAL, "shell connectivity failed");
+  if (!x_sp || !detJ || !S_fp || !Sj_sp || !nbr || !n_face) return fail(SDM_EINVAL, "shell build: NULL output");
+  if (shell_build(Nz, Nr, p, rb, rt, x_sp, detJ, S_fp, Sj_sp, nbr, n_face))
+    return fail(SDM_EINVAL, "shell connectivity failed");
   return SDM_OK;
 }
 
@@ -867,14 +1047,15 @@ sdm_status sdm_box_sizes(int nx, int ny, int nz, int periodic, int64_t* n_elem, 
 }
 
 sdm_status sdm_box_build(int nx, int ny, int nz, double Lx, double Ly, double Lz, int periodic, double warp,
-                         int p, double* x_sp, double* detJ, double* S_fp, double* S_sp, int32_t* nbr) {
+                         int p, double* x_sp, double* detJ, double* S_fp, double* Sj_sp, int32_t* nbr,
+                         double* n_face) {
   int64_t E;
   sdm_status st = sdm_box_sizes(nx, ny, nz, periodic, &E, nullptr);
   if (st != SDM_OK) return st;
   if (p < 1 || p > kNMax - 1 || !(Lx > 0) || !(Ly > 0) || !(Lz > 0))
     return fail(SDM_EINVAL, "box build: need 1 <= p <= 7 and positive lengths");
-  if (!x_sp || !detJ || !S_fp || !nbr) return fail(SDM_EINVAL, "box build: NULL output");
-  if (box_build(nx, ny, nz, Lx, Ly, Lz, periodic, warp, p, x_sp, detJ, S_fp, S_sp, nbr))
+  if (!x_sp || !detJ || !S_fp || !Sj_sp || !nbr || !n_face) return fail(SDM_EINVAL, "box build: NULL output");
+  if (box_build(nx, ny, nz, Lx, Ly, Lz, periodic, warp, p, x_sp, detJ, S_fp, Sj_sp, nbr, n_face))
     return fail(SDM_EINVAL, "box connectivity failed");
   return SDM_OK;
 }
@@ -946,7 +1127,8 @@ sdm_status sdm_mesh_bind(sdm_ctx* c, const sdm_mesh* m) {
   if (!c || !m) return fail(SDM_EINVAL, "mesh_bind: NULL argument");
   if (m->n_elem < 1 || m->n_bfaces < 0 || m->n_elem >= ((int64_t)1 << 25))
     return fail(SDM_EINVAL, "mesh_bind: 1 <= n_elem < 2^25 required");
-  if (!m->x_sp || !m->detJ || !m->S_fp || !m->nbr) return fail(SDM_EINVAL, "mesh_bind: NULL array");
+  if (!m->x_sp || !m->detJ || !m->S_fp || !m->Sj_sp || !m->nbr || !m->n_face)
+    return fail(SDM_EINVAL, "mesh_bind: NULL array");
   // validate the neighbour table on the host: every code must decode into range
   std::vector<int32_t> nb((size_t)m->n_elem * 6);
   HIP_TRY(hipSetDevice(c->device));
@@ -1040,6 +1222,89 @@ sdm_status sdm_diagnostics(sdm_ctx* c, const sdm_params* p, const double* Q, dou
   hipLaunchKernelGGL(k_diag_reduce, dim3(1), dim3(256), 0, s, (const double*)r.Rp, r.E, out);
   HIP_TRY(hipGetLastError());
   return SDM_OK;
+}
+
+
+sdm_status sdm_batch_workspace_size(int n_items, size_t* bytes) {
+  if (n_items < 1 || !bytes) return fail(SDM_EINVAL, "batch_workspace_size: n_items >= 1 and bytes required");
+  *bytes = 2 * batch_table_bytes(n_items);
+  return SDM_OK;
+}
+
+sdm_status sdm_batch_stage(const sdm_batch_item* items, int n_items, void* batch_ws, size_t batch_ws_bytes,
+                           int max_blocks, void* stream) {
+  if (!items || n_items < 1 || !batch_ws) return fail(SDM_EINVAL, "batch_stage: NULL argument or no items");
+  size_t need = 0;
+  sdm_batch_workspace_size(n_items, &need);
+  if (batch_ws_bytes < need) return fail(SDM_EINVAL, "batch_stage: batch workspace too small");
+  sdm_ctx* c0 = items[0].ctx;
+  if (!c0) return fail(SDM_EINVAL, "batch_stage: NULL context");
+  std::vector<RunDesc> all, tr;
+  std::vector<int64_t> pre_all{0}, pre_tr{0};
+  for (int k = 0; k < n_items; ++k) {
+    const sdm_batch_item& it = items[k];
+    sdm_ctx* c = it.ctx;
+    if (!c || !c->bound) return fail(SDM_ESTATE, "batch_stage: item without a bound mesh");
+    if (c->N != c0->N || c->arith != c0->arith || c->device != c0->device)
+      return fail(SDM_EINVAL, "batch_stage: items must share p, arithmetic and device");
+    if (!it.regs || !it.ws || it.n_regs < 1 || it.n_regs > 16) return fail(SDM_EINVAL, "batch_stage: bad registers");
+    const sdm_stage& st = it.stage;
+    if (st.n_in < 0 || st.n_in > 4) return fail(SDM_EINVAL, "batch_stage: 0 <= n_in <= 4");
+    auto okreg = [&](int i) { return i >= 0 && i < it.n_regs && it.regs[i] != nullptr; };
+    if (!okreg(st.cur) || !okreg(st.out)) return fail(SDM_EINVAL, "batch_stage: register index out of range");
+    for (int q = 0; q < st.n_in; ++q)
+      if (!okreg(st.in_idx[q])) return fail(SDM_EINVAL, "batch_stage: input register out of range");
+    sdm_status ps = check_params(c, it.prm);
+    if (ps != SDM_OK) return ps;
+    RunDesc r = make_desc(c, it.prm, it.regs[st.cur], it.ws);
+    for (int q = 0; q < st.n_in; ++q) {
+      r.in[q] = it.regs[st.in_idx[q]];
+      r.alpha[q] = st.alpha[q];
+    }
+    r.n_in = st.n_in;
+    r.out = it.regs[st.out];
+    r.beta_dt = st.beta * it.dt;
+    r.write_traces = 1;
+    all.push_back(r);
+    pre_all.push_back(pre_all.back() + r.E);
+    if (!st.traces_valid) {
+      tr.push_back(r);
+      pre_tr.push_back(pre_tr.back() + r.E);
+    }
+  }
+  HIP_TRY(hipSetDevice(c0->device));
+  hipStream_t s = (hipStream_t)stream;
+  // device tables: [descs | prefix] for all items, then the same for the
+  // items whose traces must be computed first
+  char* base = (char*)batch_ws;
+  const size_t tb_all = batch_table_bytes(n_items);
+  std::vector<char> host(2 * tb_all, 0);
+  auto pack = [&](size_t off, const std::vector<RunDesc>& d, const std::vector<int64_t>& pre) {
+    std::memcpy(host.data() + off, d.data(), sizeof(RunDesc) * d.size());
+    std::memcpy(host.data() + off + align256(sizeof(RunDesc) * (size_t)n_items), pre.data(), sizeof(int64_t) * pre.size());
+  };
+  pack(0, all, pre_all);
+  if (!tr.empty()) pack(tb_all, tr, pre_tr);
+  sdm_status st = stage_copy(host.data(), tr.empty() ? tb_all : 2 * tb_all, base, s);
+  if (st != SDM_OK) return st;
+  auto launch_for = [&](size_t off, int n_run, int64_t n_work) {
+    Launch L;
+    std::memset(&L, 0, sizeof L);
+    L.many = (const RunDesc*)(base + off);
+    L.prefix = (const int64_t*)(base + off + align256(sizeof(RunDesc) * (size_t)n_items));
+    L.n_run = n_run;
+    L.n_work = n_work;
+    return L;
+  };
+  const int64_t cap = max_blocks > 0 ? max_blocks : ((int64_t)1 << 30);
+  if (!tr.empty()) {
+    Launch Lt = launch_for(tb_all, (int)tr.size(), pre_tr.back());
+    Lt.n_work = pre_tr.back();
+    if ((st = run_capped(c0, 0, Lt, s, cap)) != SDM_OK) return st;
+  }
+  Launch La = launch_for(0, n_items, pre_all.back());
+  if ((st = run_capped(c0, 1, La, s, cap)) != SDM_OK) return st;
+  return run_capped(c0, 4, La, s, cap);
 }
 
 }  // extern "C"

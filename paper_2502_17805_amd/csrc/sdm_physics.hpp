@@ -16,6 +16,7 @@ struct Phys {
   T gamma;
   T Rgas;
   T cp;        // gamma R / (gamma - 1)
+  T inv_R, inv_gamma;
   T GM, Omega, nu, kappa, eta;
   T kr_scale, kr_c0, kr_c1, kr_c2, kr_w;
   T c_h, glm_a;
@@ -23,6 +24,13 @@ struct Phys {
   int32_t powell;
   int32_t wall_kind[2], wall_mag[2], wall_th[2];
 };
+
+// value of a two-wall parameter for wall group g (a select, so the
+// parameter block stays in registers)
+template <typename X>
+__device__ __forceinline__ X wsel(int g, const X (&a)[2]) {
+  return g == 0 ? a[0] : a[1];
+}
 
 // variables: 0 rho, 1-3 rho u, 4 E, 5-7 B, 8 psi ; gradients G[v*3 + j]
 
@@ -76,7 +84,7 @@ __device__ __forceinline__ void viscous_local(const T* q, const T* G, T kr, cons
   v.u[0] = q[1] * ir; v.u[1] = q[2] * ir; v.u[2] = q[3] * ir;
   v.B[0] = q[5]; v.B[1] = q[6]; v.B[2] = q[7];
   const T p = pressure(q, P);
-  const T Tt = p * ir / P.Rgas;
+  const T Tt = p * ir * P.inv_R;
   const T uu = v.u[0] * v.u[0] + v.u[1] * v.u[1] + v.u[2] * v.u[2];
   T du[3][3];
   T dp[3], drho[3];
@@ -96,10 +104,10 @@ __device__ __forceinline__ void viscous_local(const T* q, const T* G, T kr, cons
 #pragma unroll
     for (int j = 0; j < 3; ++j) v.tau[i][j] = mu * (du[i][j] + du[j][i]) + (i == j ? lam : T(0));
   const T ip = T(1) / p;
-  const T irR = ir / P.Rgas;
+  const T irR = ir * P.inv_R;
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    const T dS = P.cp * (dp[j] * ip / P.gamma - drho[j] * ir);
+    const T dS = P.cp * (dp[j] * ip * P.inv_gamma - drho[j] * ir);
     const T dT = (dp[j] - P.Rgas * Tt * drho[j]) * irR;
     v.qh[j] = -P.kappa * rho * Tt * dS - kr * rho * P.cp * dT;
   }
@@ -176,8 +184,8 @@ __device__ __forceinline__ void wall_common(const T* q, const T nh[3], int g, co
   const T rho = q[0], ir = T(1) / rho;
   const T un = (q[1] * nh[0] + q[2] * nh[1] + q[3] * nh[2]) * ir;
   const T Bn = q[5] * nh[0] + q[6] * nh[1] + q[7] * nh[2];
-  const bool cond = P.wall_mag[g] == 0;
-  const T p = P.wall_th[g] == 0 ? pressure(q, P) : rho * P.Rgas * P.T_wall[g];
+  const bool cond = wsel(g, P.wall_mag) == 0;
+  const T p = wsel(g, P.wall_th) == 0 ? pressure(q, P) : rho * P.Rgas * wsel(g, P.T_wall);
   T uc[3], Bc[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -198,7 +206,7 @@ template <typename T>
 __device__ __forceinline__ void wall_mirror(const T* q, const T nh[3], int g, const Phys<T>& P, T* qg) {
   const T mn = q[1] * nh[0] + q[2] * nh[1] + q[3] * nh[2];
   const T Bn = q[5] * nh[0] + q[6] * nh[1] + q[7] * nh[2];
-  const bool cond = P.wall_mag[g] == 0;
+  const bool cond = wsel(g, P.wall_mag) == 0;
   qg[0] = q[0];
   qg[4] = q[4];
   qg[8] = cond ? q[8] : -q[8];
@@ -209,30 +217,22 @@ __device__ __forceinline__ void wall_mirror(const T* q, const T nh[3], int g, co
   }
 }
 
-// Total outward flux at a wall point (n: outward, unnormalised; G: interior
-// gradient).  Stress-free: only the normal traction; no work term; heat flux
-// prescribed (q.n = q_wall * (-1 inner, +1 outer) |n|) or computed at a
-// fixed-T wall; current reduced to J_r (conducting) or J - J_r (radial).
+// Viscous part of the wall flux, from the viscous locals v evaluated with
+// the wall's common state and the interior gradient.  Stress-free: only the
+// normal traction; no work term; heat flux prescribed (q.n = q_wall * (-1
+// inner, +1 outer) |n|) or computed at a fixed-T wall; current reduced to J_r
+// (conducting) or J - J_r (radial).  Subtracted from F (F = F_inv - F_vis).
 template <typename T>
-__device__ __forceinline__ void wall_flux(const T* q, const T* G, T kr, const T n[3], int g,
-                                          const Phys<T>& P, T F[9]) {
-  const T nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-  const T inn = T(1) / nn;
-  const T nh[3] = {n[0] * inn, n[1] * inn, n[2] * inn};
-  T qg[9], qc[9];
-  wall_mirror(q, nh, g, P, qg);
-  rusanov(q, qg, n, P, F);
-  wall_common(q, nh, g, P, qc);
-  ViscLocal<T> v;
-  viscous_local(qc, G, kr, P, v);
+__device__ __forceinline__ void wall_viscous_sub(const ViscLocal<T>& v, const T n[3], const T nh[3], T nn,
+                                                 int g, const Phys<T>& P, T F[9]) {
   T tn[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) tn[i] = v.tau[i][0] * n[0] + v.tau[i][1] * n[1] + v.tau[i][2] * n[2];
   const T tnn = tn[0] * nh[0] + tn[1] * nh[1] + tn[2] * nh[2];
-  const T qn = P.wall_th[g] == 0 ? P.q_wall[g] * (g == 0 ? T(-1) : T(1)) * nn
-                                 : v.qh[0] * n[0] + v.qh[1] * n[1] + v.qh[2] * n[2];
+  const T qn = wsel(g, P.wall_th) == 0 ? wsel(g, P.q_wall) * (g == 0 ? T(-1) : T(1)) * nn
+                                       : v.qh[0] * n[0] + v.qh[1] * n[1] + v.qh[2] * n[2];
   const T Jn = v.J[0] * nh[0] + v.J[1] * nh[1] + v.J[2] * nh[2];
-  const bool cond = P.wall_mag[g] == 0;
+  const bool cond = wsel(g, P.wall_mag) == 0;
   T Jc[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) Jc[i] = cond ? Jn * nh[i] : v.J[i] - Jn * nh[i];

@@ -135,13 +135,13 @@ def glm_speed(Q: np.ndarray, gamma=GAMMA) -> float:
     return float(np.max(np.sqrt(u2) + np.sqrt(gamma * p / rho + b2 / rho)))
 
 
-def time_step(Q: np.ndarray, S_sp: np.ndarray, detJ: np.ndarray, c_h: float, cfl: float,
-              gamma=GAMMA) -> float:
-    """dt = cfl / max over points of lambda * sum_d |S^d| / |J| (lambda incl. c_h)."""
+def time_step(Q: np.ndarray, Sj_sp: np.ndarray, c_h: float, cfl: float, gamma=GAMMA) -> float:
+    """dt = cfl / max over points of lambda * sum_d |S^d / J| (lambda incl. c_h);
+    Sj_sp [E][3][3][N^3] holds S^d / |J| at the solution points."""
     rho = Q[:, 0]
     u2 = (Q[:, 1:4] ** 2).sum(axis=1) / rho ** 2
     b2 = (Q[:, 5:8] ** 2).sum(axis=1)
     p = (gamma - 1.0) * (Q[:, 4] - 0.5 * rho * u2 - 0.5 * b2 - 0.5 * Q[:, 8] ** 2)
     lam = np.maximum(np.sqrt(u2) + np.sqrt(gamma * p / rho + b2 / rho), c_h)
-    inv_h = np.sqrt((S_sp ** 2).sum(axis=2)).sum(axis=1) / np.abs(detJ)
+    inv_h = np.sqrt((Sj_sp ** 2).sum(axis=2)).sum(axis=1)
     return float(cfl / np.max(lam * inv_h))

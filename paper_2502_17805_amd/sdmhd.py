@@ -50,20 +50,27 @@ class Stage(C.Structure):
                 ("traces_valid", C.c_int32)]
 
 
+class BatchItem(C.Structure):
+    """Mirror of sdm_batch_item."""
+    _fields_ = [("ctx", C.c_void_p), ("prm", C.POINTER(Params)), ("regs", C.POINTER(C.c_void_p)),
+                ("n_regs", C.c_int32), ("stage", Stage), ("dt", C.c_double), ("ws", C.c_void_p)]
+
+
 class MeshDesc(C.Structure):
     """Mirror of sdm_mesh."""
     _fields_ = [("n_elem", C.c_int64), ("n_bfaces", C.c_int64), ("x_sp", C.c_void_p),
-                ("detJ", C.c_void_p), ("S_fp", C.c_void_p), ("nbr", C.c_void_p)]
+                ("detJ", C.c_void_p), ("S_fp", C.c_void_p), ("Sj_sp", C.c_void_p), ("nbr", C.c_void_p),
+                ("n_face", C.c_void_p)]
 
 
 _vp, _i64p = C.c_void_p, C.POINTER(C.c_int64)
 _lib.sdm_last_error.restype = C.c_char_p
 _lib.sdm_version.restype = C.c_char_p
 _lib.sdm_shell_sizes.argtypes = [C.c_int, C.c_int, _i64p, _i64p]
-_lib.sdm_shell_build.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double] + [_vp] * 5
+_lib.sdm_shell_build.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double] + [_vp] * 6
 _lib.sdm_box_sizes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _i64p, _i64p]
 _lib.sdm_box_build.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
-                               C.c_int, C.c_double, C.c_int] + [_vp] * 5
+                               C.c_int, C.c_double, C.c_int] + [_vp] * 6
 _lib.sdm_tables.argtypes = [C.c_int] + [_vp] * 5
 _lib.sdm_create.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]
 _lib.sdm_destroy.argtypes = [_vp]
@@ -73,17 +80,20 @@ _lib.sdm_residual.argtypes = [_vp, C.POINTER(Params), _vp, _vp, _vp, _vp]
 _lib.sdm_rk_stage.argtypes = [_vp, C.POINTER(Params), C.POINTER(C.c_void_p), C.c_int,
                               C.POINTER(Stage), C.c_double, _vp, _vp]
 _lib.sdm_diagnostics.argtypes = [_vp, C.POINTER(Params), _vp, _vp, _vp, _vp]
+_lib.sdm_batch_workspace_size.argtypes = [C.c_int, C.POINTER(C.c_size_t)]
+_lib.sdm_batch_stage.argtypes = [C.POINTER(BatchItem), C.c_int, _vp, C.c_size_t, C.c_int, _vp]
 _lib.sdm_profile_enable.argtypes = [_vp, C.c_int]
 _lib.sdm_profile_read.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
 for _f in ("sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes", "sdm_box_build", "sdm_tables",
            "sdm_create", "sdm_destroy", "sdm_mesh_bind", "sdm_workspace_size", "sdm_residual",
-           "sdm_rk_stage", "sdm_diagnostics", "sdm_profile_enable", "sdm_profile_read"):
+           "sdm_rk_stage", "sdm_diagnostics", "sdm_profile_enable", "sdm_profile_read",
+           "sdm_batch_workspace_size", "sdm_batch_stage"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTED = ("sdm_last_error", "sdm_version", "sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes",
             "sdm_box_build", "sdm_tables", "sdm_create", "sdm_destroy", "sdm_mesh_bind",
             "sdm_workspace_size", "sdm_residual", "sdm_rk_stage", "sdm_diagnostics",
-            "sdm_profile_enable", "sdm_profile_read")
+            "sdm_profile_enable", "sdm_profile_read", "sdm_batch_workspace_size", "sdm_batch_stage")
 KERNELS = ("traces", "volume", "volume_diag", "finish_residual", "finish_stage")
 
 
@@ -131,8 +141,9 @@ class Mesh:
     x_sp: np.ndarray
     detJ: np.ndarray
     S_fp: np.ndarray
-    S_sp: np.ndarray
+    Sj_sp: np.ndarray
     nbr: np.ndarray
+    n_face: np.ndarray
 
     @property
     def N(self):
@@ -143,15 +154,15 @@ def _alloc(p, E, NB):
     N = p + 1
     N3, NF = N ** 3, (N + 1) * N * N
     return Mesh(p, E, NB, np.zeros((E, 3, N3)), np.zeros((E, N3)), np.zeros((E, 3, 3, NF)),
-                np.zeros((E, 3, 3, N3)), np.zeros((E, 6), dtype=np.int32))
+                np.zeros((E, 3, 3, N3)), np.zeros((E, 6), dtype=np.int32), np.zeros((E, 6, 3, N * N)))
 
 
 def shell(Nz: int, Nr: int, p: int, rb: float = 0.70, rt: float = 0.98) -> Mesh:
     E, NB = C.c_int64(), C.c_int64()
     _check(_lib.sdm_shell_sizes(Nz, Nr, C.byref(E), C.byref(NB)))
     m = _alloc(p, E.value, NB.value)
-    _check(_lib.sdm_shell_build(Nz, Nr, p, rb, rt, _p(m.x_sp), _p(m.detJ), _p(m.S_fp), _p(m.S_sp),
-                                _p(m.nbr)))
+    _check(_lib.sdm_shell_build(Nz, Nr, p, rb, rt, _p(m.x_sp), _p(m.detJ), _p(m.S_fp), _p(m.Sj_sp),
+                                _p(m.nbr), _p(m.n_face)))
     return m
 
 
@@ -160,7 +171,7 @@ def box(nx, ny, nz, p, L=(1.0, 1.0, 1.0), periodic=7, warp=0.0) -> Mesh:
     _check(_lib.sdm_box_sizes(nx, ny, nz, periodic, C.byref(E), C.byref(NB)))
     m = _alloc(p, E.value, NB.value)
     _check(_lib.sdm_box_build(nx, ny, nz, L[0], L[1], L[2], periodic, warp, p, _p(m.x_sp), _p(m.detJ),
-                              _p(m.S_fp), _p(m.S_sp), _p(m.nbr)))
+                              _p(m.S_fp), _p(m.Sj_sp), _p(m.nbr), _p(m.n_face)))
     return m
 
 
@@ -223,8 +234,9 @@ class Solver:
         self._h = h
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(self.dev)  # noqa: E731
         self.x_sp, self.detJ, self.S_fp, self.nbr = t(mesh.x_sp), t(mesh.detJ), t(mesh.S_fp), t(mesh.nbr)
+        self.n_face, self.Sj_sp = t(mesh.n_face), t(mesh.Sj_sp)
         md = MeshDesc(mesh.E, mesh.NB, self.x_sp.data_ptr(), self.detJ.data_ptr(), self.S_fp.data_ptr(),
-                      self.nbr.data_ptr())
+                      self.Sj_sp.data_ptr(), self.nbr.data_ptr(), self.n_face.data_ptr())
         _check(_lib.sdm_mesh_bind(h, C.byref(md)))
         nb = C.c_size_t()
         _check(_lib.sdm_workspace_size(h, C.byref(nb)))

@@ -1,0 +1,255 @@
+"""Continuous-batching server for ensembles of independent SD-MHD runs on one GPU.
+
+Requests (shell size, polynomial degree, density scale heights, seed, number of
+SSPRK(5,3) steps, arithmetic) arrive over time.  A request is admitted as soon
+as a slot is free and its device memory fits the HBM budget; its mesh, state
+registers and workspace then stay resident on the device until it finishes.
+Every scheduler iteration advances each active run by one SSPRK(5,3) step:
+for each of the five stages, the stages of all active runs with the same
+degree and arithmetic go into one shared launch sequence (sdm_batch_stage:
+a grid-stride loop over the concatenated elements of all runs), so runs that
+arrive while others are on the GPU join the same launches.  A run's arithmetic
+is exactly that of a single-run stage, so its result is bitwise the same alone
+and in any mix.
+"""
+from __future__ import annotations
+
+import collections
+import ctypes as C
+import dataclasses
+import time
+
+import numpy as np
+
+from . import inputs as inp
+from . import sdmhd as sd
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    Nz: int
+    Nr: int
+    p: int
+    N_rho: float
+    seed: int
+    steps: int
+    arith: int = 0
+    arrival: float = 0.0  # seconds after the server starts
+
+    @property
+    def dof(self):
+        return 6 * self.Nz * self.Nz * self.Nr * (self.p + 1) ** 3
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float
+    done: float
+    steps: int
+    dof: int
+    diag: np.ndarray
+    state: np.ndarray | None = None
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+
+class _MeshCache:
+    """Host meshes and their device copies, shared by runs of equal shape."""
+
+    def __init__(self, device):
+        self.device = device
+        self.host = {}
+        self.dev = {}
+        self.users = collections.Counter()
+
+    def get(self, Nz, Nr, p):
+        import torch
+        key = (Nz, Nr, p)
+        if key not in self.host:
+            self.host[key] = sd.shell(Nz, Nr, p)
+        if key not in self.dev:
+            m = self.host[key]
+            t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(self.device)  # noqa: E731
+            self.dev[key] = dict(x_sp=t(m.x_sp), detJ=t(m.detJ), S_fp=t(m.S_fp), Sj_sp=t(m.Sj_sp),
+                                 nbr=t(m.nbr), n_face=t(m.n_face))
+        self.users[key] += 1
+        return self.host[key], self.dev[key]
+
+    def release(self, Nz, Nr, p):
+        key = (Nz, Nr, p)
+        self.users[key] -= 1
+        if self.users[key] == 0:
+            del self.dev[key]  # device copy freed; the host mesh stays cached
+
+    @staticmethod
+    def device_bytes(Nz, Nr, p):
+        E, N = 6 * Nz * Nz * Nr, p + 1
+        N3, NF = N ** 3, (N + 1) * N * N
+        return 8 * E * (3 * N3 + N3 + 9 * NF + 9 * N3 + 18 * N * N) + 4 * E * 6
+
+
+def request_bytes(q: Request) -> int:
+    """Device bytes a request holds while resident: four FP64 state
+    registers, the workspace (face traces, viscous traces, partial residual
+    in the arithmetic type), and its mesh arrays (counted per request)."""
+    E, N = 6 * q.Nz * q.Nz * q.Nr, q.p + 1
+    rs = 4 if q.arith else 8
+    ws = rs * E * (6 * 9 * N * N + 6 * 7 * N * N + 9 * N ** 3) + 3 * 256
+    return 4 * 8 * 9 * q.dof + ws + _MeshCache.device_bytes(q.Nz, q.Nr, q.p)
+
+
+class _Run:
+    """One admitted request resident on the device."""
+
+    def __init__(self, req: Request, cache: _MeshCache, device, t_admit):
+        import torch
+        self.req = req
+        self.t_admit = t_admit
+        mesh, dev = cache.get(req.Nz, req.Nr, req.p)
+        self.mesh, self.devmesh = mesh, dev
+        h = C.c_void_p()
+        sd._check(sd._lib.sdm_create(device.index or 0, req.p, req.arith, C.byref(h)))
+        self.ctx = h
+        md = sd.MeshDesc(mesh.E, mesh.NB, dev["x_sp"].data_ptr(), dev["detJ"].data_ptr(), dev["S_fp"].data_ptr(),
+                         dev["Sj_sp"].data_ptr(), dev["nbr"].data_ptr(), dev["n_face"].data_ptr())
+        sd._check(sd._lib.sdm_mesh_bind(h, C.byref(md)))
+        nb = C.c_size_t()
+        sd._check(sd._lib.sdm_workspace_size(h, C.byref(nb)))
+        self.ws = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+        bg = inp.Background(req.N_rho)
+        Q = inp.shell_state(mesh.x_sp, bg, req.seed)
+        pr = inp.run_params(req.seed, bg)
+        ch = inp.glm_speed(Q)
+        pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
+        self.prm = sd.make_params(**pr)
+        self.dt = inp.time_step(Q, mesh.Sj_sp, ch, 0.1)
+        shp = (mesh.E, 9, mesh.N ** 3)
+        self.regs = [torch.empty(shp, dtype=torch.float64, device=device) for _ in range(4)]
+        self.regs[0].copy_(torch.from_numpy(Q))
+        self.reg_ptrs = (C.c_void_p * 4)(*[r.data_ptr() for r in self.regs])
+        self.steps_done = 0
+        self.traces_valid = False
+        self.bytes = request_bytes(req)
+
+    def item(self, cur, inputs, beta, out):
+        st = sd.Stage()
+        st.n_in = len(inputs)
+        for k, (idx, al) in enumerate(inputs):
+            st.in_idx[k] = idx
+            st.alpha[k] = al
+        st.cur, st.out, st.beta = cur, out, beta
+        st.traces_valid = 1 if self.traces_valid else 0
+        self.traces_valid = True  # every stage leaves the traces of its output
+        return sd.BatchItem(self.ctx.value, C.pointer(self.prm), self.reg_ptrs, 4, st, self.dt, self.ws.data_ptr())
+
+    def close(self, cache):
+        sd._lib.sdm_destroy(self.ctx)
+        cache.release(self.req.Nz, self.req.Nr, self.req.p)
+
+
+class Server:
+    """Admission by slots and HBM budget; one batched SSPRK step per iteration."""
+
+    def __init__(self, budget_bytes: float = 200e9, max_slots: int = 64, device: int = 0, max_blocks: int = 0,
+                 keep_states: bool = False):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.budget = budget_bytes
+        self.max_slots = max_slots
+        self.max_blocks = max_blocks
+        self.keep_states = keep_states
+        self.cache = _MeshCache(self.device)
+        nb = C.c_size_t()
+        sd._check(sd._lib.sdm_batch_workspace_size(max_slots, C.byref(nb)))
+        self.batch_ws_bytes = int(nb.value)
+        self.batch_ws = torch.empty(self.batch_ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stats = {}
+
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _step_all(self, active):
+        groups = collections.defaultdict(list)
+        for r in active:
+            groups[(r.req.p, r.req.arith)].append(r)
+        stages = sd.ssp53_stages()
+        for cur, inputs, beta, out in stages:
+            for runs in groups.values():
+                items = (sd.BatchItem * len(runs))(*[r.item(cur, inputs, beta, out) for r in runs])
+                sd._check(sd._lib.sdm_batch_stage(items, len(runs), self.batch_ws.data_ptr(), self.batch_ws_bytes,
+                                                  self.max_blocks, self._stream()))
+        for r in active:
+            r.steps_done += 1
+
+    def run(self, requests):
+        torch = self.torch
+        pending = collections.deque(sorted(requests, key=lambda q: q.arrival))
+        active, results = [], []
+        used, peak_used, peak_active, iters, queued_wait = 0, 0, 0, 0, 0
+        t0 = time.perf_counter()
+        while pending or active:
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now and len(active) < self.max_slots:
+                q = pending[0]
+                if used + request_bytes(q) > self.budget:
+                    queued_wait += 1
+                    break
+                pending.popleft()
+                r = _Run(q, self.cache, self.device, time.perf_counter() - t0)
+                used += r.bytes
+                active.append(r)
+            peak_used = max(peak_used, used)
+            peak_active = max(peak_active, len(active))
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, min(0.002, pending[0].arrival - (time.perf_counter() - t0))))
+                continue
+            self._step_all(active)
+            iters += 1
+            torch.cuda.synchronize(self.device)
+            tnow = time.perf_counter() - t0
+            still = []
+            for r in active:
+                if r.steps_done >= r.req.steps:
+                    diag = np.zeros(16)
+                    out = torch.zeros(16, dtype=torch.float64, device=self.device)
+                    sd._check(sd._lib.sdm_diagnostics(r.ctx, C.byref(r.prm), r.regs[0].data_ptr(), out.data_ptr(),
+                                                      r.ws.data_ptr(), self._stream()))
+                    diag = out.cpu().numpy()
+                    state = r.regs[0].cpu().numpy() if self.keep_states else None
+                    results.append(Result(r.req.rid, r.req.arrival, r.t_admit, tnow, r.steps_done, r.req.dof,
+                                          diag, state))
+                    used -= r.bytes
+                    r.close(self.cache)
+                else:
+                    still.append(r)
+            active = still
+        makespan = time.perf_counter() - t0
+        lat = np.array([x.latency for x in results])
+        work = sum(x.dof * 5 * x.steps for x in results)
+        self.stats = dict(requests=len(results), makespan_s=makespan, iterations=iters,
+                          p50_latency_s=float(np.percentile(lat, 50)) if len(lat) else None,
+                          p99_latency_s=float(np.percentile(lat, 99)) if len(lat) else None,
+                          dof_stage_per_s=work / makespan if makespan > 0 else None,
+                          peak_active=peak_active, peak_bytes=peak_used, admissions_deferred=queued_wait)
+        return sorted(results, key=lambda x: x.rid), self.stats
+
+
+def poisson_requests(n: int = 64, mean_gap_s: float = 0.020, steps: int = 500, seed: int = 7,
+                     meshes=((4, 3), (8, 4), (12, 8)), degrees=(3, 5), n_rhos=(3.0, 5.0), arith: int = 0):
+    """The served-ensemble workload: Poisson arrivals, mesh, degree and N_rho
+    drawn uniformly, run seeds 1000 + request index."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t, out = 0.0, []
+    for i in range(n):
+        t += rng.exponential(mean_gap_s)
+        Nz, Nr = meshes[rng.integers(len(meshes))]
+        out.append(Request(i, int(Nz), int(Nr), int(degrees[rng.integers(len(degrees))]),
+                           float(n_rhos[rng.integers(len(n_rhos))]), 1000 + i, steps, arith, t))
+    return out

@@ -110,7 +110,7 @@ def test_ssprk53_steps_c1(sd, oracle):
     state against the oracle's."""
     import torch
     ml, mo, bg, Q, pr = _c1(sd, oracle)
-    dt = inp.time_step(Q, mo.get("S_sp"), mo.get("detJ_sp"), pr["c_h"], 0.1)
+    dt = inp.time_step(Q, mo.get("S_sp") / mo.get("detJ_sp")[:, None, None, :], pr["c_h"], 0.1)
     s = sd.Solver(ml)
     pg, po, _ = _both(sd, oracle, pr)
     s.set_state(Q)

@@ -38,7 +38,8 @@ def test_shell_geometry_agrees(sd, oracle, p, Nz, Nr):
     m = sd.shell(Nz, Nr, p)
     o = oracle.Mesh.shell(p + 1, Nz, Nr)
     assert m.E == o.E and m.NB == o.NB
-    for name, arr in (("x_sp", m.x_sp), ("detJ_sp", m.detJ), ("S_fp", m.S_fp), ("S_sp", m.S_sp)):
+    for name, arr in (("x_sp", m.x_sp), ("detJ_sp", m.detJ), ("S_fp", m.S_fp),
+                      ("S_sp", m.Sj_sp * m.detJ[:, None, None, :])):
         ref = o.get(name)
         np.testing.assert_allclose(arr, ref, rtol=0, atol=1e-13 * np.abs(ref).max(), err_msg=name)
     onb = o.get("nbr")
@@ -66,3 +67,32 @@ def test_errors_are_reported(sd):
         sd.shell(0, 1, 5)
     with pytest.raises(sd.SdmError):
         sd.box(2, 3, 3, 5, periodic=1)  # periodic direction needs >= 3 elements
+
+
+def test_face_normals_symmetric(sd):
+    """n_face is the symmetric outward normal: exact negatives across every
+    interior face point, the element's own outward metric vector on walls."""
+    N = 6
+    m = sd.shell(2, 2, N - 1)
+
+    def fp(d, f, a, b):
+        return f + (N + 1) * (a + N * b) if d == 0 else (a + N * (f + (N + 1) * b) if d == 1 else a + N * (b + N * f))
+
+    def omap(o, a, b):
+        p, q = (b, a) if o & 4 else (a, b)
+        return (N - 1 - p if o & 1 else p), (N - 1 - q if o & 2 else q)
+
+    for e in range(m.E):
+        for f in range(6):
+            code = int(m.nbr[e, f])
+            for b in range(N):
+                for a in range(N):
+                    n = m.n_face[e, f, :, a + N * b]
+                    sown = (1 if f % 2 else -1) * m.S_fp[e, f // 2, :, fp(f // 2, N if f % 2 else 0, a, b)]
+                    if code >= 0:
+                        en, fn, o = code >> 6, (code >> 3) & 7, code & 7
+                        a2, b2 = omap(o, a, b)
+                        assert np.array_equal(n, -m.n_face[en, fn, :, a2 + N * b2])
+                        assert np.abs(n - sown).max() < 1e-12 * np.abs(sown).max()
+                    else:
+                        assert np.array_equal(n, sown)
