@@ -39,19 +39,40 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
-def kernel_bytes(kind, N, E, rs, n_in_avg):
-    """Algorithmic bytes one launch of a kernel moves (each input read once,
-    each output written once; rs = bytes of the residual arithmetic type)."""
+def alg_bytes(kind, N, E, n_extra=1.2):
+    """Algorithmic HBM bytes of one launch: what the method itself must move,
+    each once (state, RK registers, stored geometry), independent of the
+    implementation's intermediate buffers (face traces, partial residuals).
+
+    volume:       the state 9N^3, |J| and S^d/|J| at the SPs 10N^3, the
+                  metric S^d at the own-family flux points 9(N+1)N^2 and the
+                  SP positions 3N^3 (gravity), FP64.
+    finish_stage: the extra RK registers the Shu-Osher combination reads
+                  (n_extra on average: 0, 0, 1, 2, 3 over the five stages of
+                  SSPRK(5,3)) and the stage output, 9N^3 each, FP64.
+    stage:        the sum, i.e. 8 [(R_in + 1) 9N^3 + 10N^3 + 9(N+1)N^2 + 3N^3]
+                  per element with R_in = 1 + n_extra.
+    """
+    N2, N3 = N * N, N ** 3
+    vol = 8 * (9 * N3 + 10 * N3 + 9 * (N + 1) * N2 + 3 * N3)
+    fin = 8 * 9 * N3 * (n_extra + 1)
+    per = {"volume": vol, "finish_stage": fin, "stage": vol + fin}.get(kind)
+    return None if per is None else per * E
+
+
+def alg_flops(N):
+    """FP64 flops of one residual evaluation per element, estimated from the
+    operations of the SD scheme (Sec. 3): the four tensor contractions
+    (Q to the flux points of each family, the derivative of the flux-point
+    polynomial at the SPs, the 27 gradient components to the flux points,
+    the flux divergence) as multiply-adds, the chain rule, and the pointwise
+    work per flux point (inviscid + viscous flux and its contraction with
+    S^d, about 300 flops), per face point (Rusanov + BR1, about 150) and per
+    SP (sources and update, about 100)."""
     N2, N3, NF = N * N, N ** 3, (N + 1) * N * N
-    if kind == "volume":
-        per = 8 * (9 * N3 + 9 * NF + N3 + 3 * N3 + 6 * 3 * N2) + 24 + rs * (6 * 9 * N2 + 9 * N3 + 6 * 7 * N2)
-    elif kind == "finish_stage":
-        per = 8 * (N3 + n_in_avg * 9 * N3 + 9 * N3) + 24 + rs * (9 * N3 + 6 * 7 * N2 + 6 * 9 * N2)
-    elif kind == "traces":
-        per = 8 * 9 * N3 + rs * 6 * 9 * N2
-    else:
-        return None
-    return per * E
+    mac = 3 * 9 * NF * N + 3 * 9 * N3 * (N + 1) + 27 * 3 * NF * N + 3 * 9 * N3 * (N + 1) + 27 * 3 * N3
+    point = 300 * 3 * NF + 150 * 6 * N2 // 2 + 100 * N3
+    return 2 * mac + point
 
 
 def kernel_source_hash():
@@ -126,6 +147,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cfl", type=float, default=0.1)
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="BYTES",
+                    help="first run a plain device copy of BYTES bytes (read BYTES, write BYTES) three "
+                         "times, the reference that HBM byte counters are scaled by")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): sharding the shell "
@@ -135,6 +159,16 @@ def main():
     import torch
     from paper_2502_17805_amd import inputs as inp
     from paper_2502_17805_amd import sdmhd as sd
+
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+        print(f"# copy calibration: 3 x {8 * n} bytes read and written", file=sys.stderr, flush=True)
 
     cfg = CONFIGS[args.config]
     Nz, Nr, p, N_rho, seed = cfg
@@ -162,17 +196,26 @@ def main():
     ms, wall, prof, diag = res[0]
     stages = 5 * args.steps
     value = dof * stages / (ms * 1e-3)
-    # roofline of the dominant kernel (largest summed time)
+    # roofline of the dominant kernel (largest summed time), from the HIP
+    # events the library records around each launch on its stream
     dom = max(prof, key=lambda k: prof[k][0])
     avg_ms = prof[dom][0] / prof[dom][1]
-    n_in_avg = (1 + 2 + 3 + 4) / 5.0 + 0.0  # extra register reads per stage besides the current state
-    bytes_launch = kernel_bytes(dom, N, mesh.E, 8, n_in_avg)
+    bytes_launch = alg_bytes(dom, N, mesh.E)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if bytes_launch else None
     traffic = measured_traffic(dom, args.config, 0)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
-            "kernel": f"k_volume<N={N},double>" if dom == "volume" else dom,
-            "avg_launch_ms": avg_ms}
+            "kernel": f"k_volume<{N}, double>" if dom == "volume" else dom, "avg_launch_ms": avg_ms,
+            "alg_bytes_per_launch": bytes_launch}
+    if dom == "volume":
+        fl = alg_flops(N) * mesh.E
+        roof["fp64_tflops"] = fl / (avg_ms * 1e-3) / 1e12
+        roof["fp64_frac"] = roof["fp64_tflops"] / FP64_PEAK_TFLOPS
+    # the whole stage (all kernels of one RK stage) against the same bounds
+    t_stage = ms * 1e-3 / stages
+    stage_roof = {"alg_bytes": alg_bytes("stage", N, mesh.E), "ms": t_stage * 1e3,
+                  "hbm_frac": alg_bytes("stage", N, mesh.E) / t_stage / 1e9 / HBM_PEAK_GBS,
+                  "fp64_frac": alg_flops(N) * mesh.E / t_stage / 1e12 / FP64_PEAK_TFLOPS}
     out = {
         "metric": "SD-MHD DOF*RK-stage updates/s (FP64)",
         "value": value,
@@ -190,6 +233,7 @@ def main():
                                f"{dof} solution points x 9 vars, N_rho={N_rho:g}, SSPRK(5,3) step = 5 stages",
                    "elements": mesh.E, "p": p, "dof": dof, "stages_per_step": 5, "parallelism": "single GPU"},
         "roofline": roof,
+        "stage_roofline": stage_roof,
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
     }
     if 1 in res:

@@ -91,25 +91,40 @@ struct Launch {
   const int64_t* prefix;        // [n_run + 1] element offsets of the runs
   int32_t n_run;
   int64_t n_work;               // total elements
+  int64_t w0;                   // first work item of this launch (one per workgroup)
 };
 
-__device__ __forceinline__ void locate(const Launch& L, int64_t w, const RunDesc*& rd, int64_t& e) {
-  if (L.many == nullptr) {
-    rd = &L.one;
-    e = w;
-    return;
-  }
-  int lo = 0, hi = L.n_run - 1;
-  while (lo < hi) {  // last run with prefix <= w
-    const int mid = (lo + hi + 1) >> 1;
-    if (L.prefix[mid] <= w) lo = mid; else hi = mid - 1;
-  }
-  rd = &L.many[lo];
-  e = w - L.prefix[lo];
-}
+// Device-side view of one run's descriptor with every array pointer in the
+// global address space, so that element data moves with global (not flat)
+// loads and stores and LDS waits never wait on them.
+#define GBL __attribute__((address_space(1)))
 
 template <typename T>
-__device__ __forceinline__ Phys<T> cvt_phys(const Phys<double>& p) {
+struct Run {
+  int64_t e;  // element index within the run
+  const GBL double* x_sp;
+  const GBL double* detJ;
+  const GBL double* S_fp;
+  const GBL double* Sj_sp;
+  const GBL int32_t* nbr;
+  const GBL double* n_face;
+  const GBL double* ghost;
+  const GBL double* Q;
+  GBL T* Qtr;
+  GBL T* Vtr;
+  GBL T* Rp;
+  GBL double* R;
+  const GBL double* in[4];
+  double alpha[4];
+  int32_t n_in;
+  int32_t write_traces;
+  GBL double* out;
+  double beta_dt;
+  Phys<T> P;
+};
+
+template <typename T, typename S>
+__device__ __forceinline__ Phys<T> cvt_phys(S& p) {
   Phys<T> o;
   o.gm1 = (T)p.gm1; o.gamma = (T)p.gamma; o.Rgas = (T)p.Rgas; o.cp = (T)p.cp;
   o.inv_R = (T)p.inv_R; o.inv_gamma = (T)p.inv_gamma;
@@ -123,6 +138,53 @@ __device__ __forceinline__ Phys<T> cvt_phys(const Phys<double>& p) {
   o.wall_mag[0] = p.wall_mag[0]; o.wall_mag[1] = p.wall_mag[1];
   o.wall_th[0] = p.wall_th[0]; o.wall_th[1] = p.wall_th[1];
   return o;
+}
+
+template <typename T, typename S>
+__device__ __forceinline__ void fill_run(Run<T>& r, S& d) {
+  r.x_sp = (const GBL double*)d.x_sp;
+  r.detJ = (const GBL double*)d.detJ;
+  r.S_fp = (const GBL double*)d.S_fp;
+  r.Sj_sp = (const GBL double*)d.Sj_sp;
+  r.nbr = (const GBL int32_t*)d.nbr;
+  r.n_face = (const GBL double*)d.n_face;
+  r.ghost = (const GBL double*)d.ghost;
+  r.Q = (const GBL double*)d.Q;
+  r.Qtr = (GBL T*)d.Qtr;
+  r.Vtr = (GBL T*)d.Vtr;
+  r.Rp = (GBL T*)d.Rp;
+  r.R = (GBL double*)d.R;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r.in[k] = (const GBL double*)d.in[k];
+    r.alpha[k] = d.alpha[k];
+  }
+  r.n_in = d.n_in;
+  r.write_traces = d.write_traces;
+  r.out = (GBL double*)d.out;
+  r.beta_dt = d.beta_dt;
+  r.P = cvt_phys<T>(d.P);
+}
+
+// the run and element of work item w (batched: last run whose element offset
+// is <= w, by binary search over the prefix table)
+template <typename T>
+__device__ __forceinline__ Run<T> view(const Launch& L, int64_t w) {
+  Run<T> r;
+  if (L.many == nullptr) {
+    fill_run(r, L.one);
+    r.e = w;
+    return r;
+  }
+  const GBL int64_t* pre = (const GBL int64_t*)L.prefix;
+  int lo = 0, hi = L.n_run - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= w) lo = mid; else hi = mid - 1;
+  }
+  fill_run(r, ((const GBL RunDesc*)L.many)[lo]);
+  r.e = w - pre[lo];
+  return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -164,8 +226,7 @@ __device__ __forceinline__ T line_interp(const T* f, const T* w, int s0, int st)
 // radiative diffusivity sampled at the SPs and interpolated the same way.
 template <int N, typename T>
 __device__ __forceinline__ T interp_point(const T* sQ, const T* sG, const T* w, int s0, int st, T qf[9],
-                                          T gf[27], bool use_kr, const RunDesc* rd, int64_t e,
-                                          const Phys<T>& P) {
+                                          T gf[27], bool use_kr, const Run<T>& R) {
   constexpr int N3 = N * N * N;
 #pragma unroll
   for (int v = 0; v < 9; ++v) qf[v] = T(0);
@@ -181,9 +242,9 @@ __device__ __forceinline__ T interp_point(const T* sQ, const T* sG, const T* w, 
 #pragma unroll
     for (int k = 0; k < 27; ++k) gf[k] += wi * sG[k * N3 + sidx];
     if (use_kr) {
-      const T x[3] = {(T)rd->x_sp[(e * 3 + 0) * N3 + sidx], (T)rd->x_sp[(e * 3 + 1) * N3 + sidx],
-                      (T)rd->x_sp[(e * 3 + 2) * N3 + sidx]};
-      kf += wi * kappa_r(x, P);
+      const T x[3] = {(T)R.x_sp[(R.e * 3 + 0) * N3 + sidx], (T)R.x_sp[(R.e * 3 + 1) * N3 + sidx],
+                      (T)R.x_sp[(R.e * 3 + 2) * N3 + sidx]};
+      kf += wi * kappa_r(x, R.P);
     }
   }
   return kf;
@@ -193,10 +254,9 @@ __device__ __forceinline__ T interp_point(const T* sQ, const T* sG, const T* w, 
 // neighbour's stored trace (orientation-mapped), the ghost state on
 // Dirichlet faces; nothing on walls (their state is built from the own one).
 template <int N, typename T>
-__device__ __forceinline__ void load_outside(const RunDesc* rd, int64_t e, int f, int ab, int32_t code,
-                                             const T* Qtr, const Phys<T>& P, T q[9], T n[3]) {
+__device__ __forceinline__ void load_outside(const Run<T>& R, int f, int ab, int32_t code, T q[9], T n[3]) {
   constexpr int N2 = N * N;
-  const double* nf = rd->n_face + (e * 6 + f) * 3 * N2 + ab;
+  const GBL double* nf = R.n_face + (R.e * 6 + f) * 3 * N2 + ab;
   n[0] = (T)nf[0];
   n[1] = (T)nf[N2];
   n[2] = (T)nf[2 * N2];
@@ -205,14 +265,14 @@ __device__ __forceinline__ void load_outside(const RunDesc* rd, int64_t e, int f
     const int fn = (code >> 3) & 7, o = code & 7;
     int a2, b2;
     omap<N>(o, ab % N, ab / N, a2, b2);
-    const T* tn = Qtr + (en * 6 + fn) * 9 * N2 + a2 + N * b2;
+    const GBL T* tn = R.Qtr + (en * 6 + fn) * 9 * N2 + a2 + N * b2;
 #pragma unroll
     for (int v = 0; v < 9; ++v) q[v] = tn[v * N2];
   } else {
     const int c2 = -code - 1, g = c2 & 3;
     const int64_t bf = c2 >> 2;
-    if (g == 2 || wsel(g, P.wall_kind) == 1) {
-      const double* gh = rd->ghost + bf * 9 * N2 + ab;
+    if (g == 2 || wsel(g, R.P.wall_kind) == 1) {
+      const GBL double* gh = R.ghost + bf * 9 * N2 + ab;
 #pragma unroll
       for (int v = 0; v < 9; ++v) q[v] = (T)gh[v * N2];
     } else {
@@ -223,27 +283,44 @@ __device__ __forceinline__ void load_outside(const RunDesc* rd, int64_t e, int f
 }
 
 // ---------------------------------------------------------------------------
+// the basis tables a thread indexes by its own point (not uniformly across
+// the wave) are staged once per workgroup in LDS: I [N+1][N], D [N][N+1]
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__device__ __forceinline__ void stage_tables(T* sI, T* sD) {
+  const DevTab<T>& tb = tab<T>(N);
+  for (int i = threadIdx.x; i < (N + 1) * N; i += blockDim.x) {
+    sI[i] = tb.I[i / N][i % N];
+    sD[i] = tb.D[i / (N + 1)][i % (N + 1)];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // k_traces: face traces of Q (used before a run's first stage)
 // ---------------------------------------------------------------------------
 template <int N, typename T>
 __global__ __launch_bounds__(block_threads<N>()) void k_traces(Launch L) {
   constexpr int N2 = N * N, N3 = N2 * N, BS = block_threads<N>();
   __shared__ T sQ[9 * N3];
-  const DevTab<T>& tb = tab<T>(N);
-  for (int64_t w = blockIdx.x; w < L.n_work; w += gridDim.x) {
-    const RunDesc* rd;
-    int64_t e;
-    locate(L, w, rd, e);
-    const double* Qe = rd->Q + e * 9 * N3;
+  __shared__ T sI[(N + 1) * N], sD[N * (N + 1)];
+  stage_tables<N>(sI, sD);
+  {
+    // one element per workgroup; no loop, so nothing per element is kept
+    // live across elements
+    const int64_t w = L.w0 + blockIdx.x;
+    if (w >= L.n_work) return;
+    const Run<T> R = view<T>(L, w);
+    const GBL double* Qe = R.Q + R.e * 9 * N3;
     for (int i = threadIdx.x; i < 9 * N3; i += BS) sQ[i] = (T)Qe[i];
     __syncthreads();
-    T* tr = (T*)rd->Qtr + e * 6 * 9 * N2;
+    GBL T* tr = R.Qtr + R.e * 6 * 9 * N2;
     for (int it = threadIdx.x; it < 6 * 9 * N2; it += BS) {
       const int ab = it % N2, fv = it / N2, v = fv % 9, f = fv / 9;
-      const int d = f >> 1, fe = (f & 1) ? N : 0;
+      const int d = f >> 1;
+      const T* wI = sI + ((f & 1) ? N : 0) * N;
       T s = T(0);
 #pragma unroll
-      for (int i = 0; i < N; ++i) s += tb.I[fe][i] * sQ[v * N3 + sp_line<N>(d, ab % N, ab / N, i)];
+      for (int i = 0; i < N; ++i) s += wI[i] * sQ[v * N3 + sp_line<N>(d, ab % N, ab / N, i)];
       tr[it] = s;
     }
     __syncthreads();
@@ -254,12 +331,12 @@ __global__ __launch_bounds__(block_threads<N>()) void k_traces(Launch L) {
 // k_volume
 // ---------------------------------------------------------------------------
 // waves per SIMD the volume pass is compiled for (its register budget is
-// 512 / waves): FP64 keeps the whole budget, FP32 fits two waves
+// 512 / waves): FP64 two (LDS also admits two workgroups per CU), FP32 four
 #ifndef SDM_VOLUME_WAVES_F64
-#define SDM_VOLUME_WAVES_F64 1
+#define SDM_VOLUME_WAVES_F64 2
 #endif
 #ifndef SDM_VOLUME_WAVES_F32
-#define SDM_VOLUME_WAVES_F32 2
+#define SDM_VOLUME_WAVES_F32 4
 #endif
 template <typename T>
 constexpr int volume_waves() {
@@ -271,7 +348,7 @@ __global__ __launch_bounds__(block_threads<N>()) __attribute__((amdgpu_waves_per
 void k_volume(Launch L) {
   constexpr int N2 = N * N, N3 = N2 * N, NP = N + 1, NF = NP * N2, BS = block_threads<N>();
   constexpr int NI = N2 * (N - 1);  // interior flux points of one family
-  constexpr int UN = (9 * NF > 9 * 6 * N2) ? 9 * NF : 9 * 6 * N2;
+  constexpr int UN = (9 * NI > 9 * 6 * N2) ? 9 * NI : 9 * 6 * N2;
   // a thread keeps its own face point / interior flux points across phases
   // when one pass covers them all
   constexpr bool FACE_REG = 6 * N2 <= BS;
@@ -280,20 +357,24 @@ void k_volume(Launch L) {
   __shared__ T sG[27 * N3];
   __shared__ T sU[UN];  // face jumps (common value - own trace), then fluxes
   __shared__ double sRed[BS / 64][10];
+  __shared__ T sI[(N + 1) * N], sD[N * (N + 1)];
   static_assert(BS >= N3, "one solution point per thread");
   const DevTab<T>& tb = tab<T>(N);
   const int tid = threadIdx.x;
   const int ia0 = tid % N, ia1 = (tid / N) % N, ia2 = tid / N2;  // this thread's SP (tid < N3)
+  stage_tables<N>(sI, sD);
 
-  for (int64_t w = blockIdx.x; w < L.n_work; w += gridDim.x) {
-    const RunDesc* rd;
-    int64_t e;
-    locate(L, w, rd, e);
-    const Phys<T> P = cvt_phys<T>(rd->P);
-    const double* Qe = rd->Q + e * 9 * N3;
-    const double* Se = rd->S_fp + e * 9 * NF;
-    const int32_t* nb6 = rd->nbr + e * 6;
-    const T* Qtr = (const T*)rd->Qtr;
+  {
+    // one element per workgroup; no loop, so nothing per element is kept
+    // live across elements
+    const int64_t w = L.w0 + blockIdx.x;
+    if (w >= L.n_work) return;
+    const Run<T> R = view<T>(L, w);
+    const int64_t e = R.e;
+    const Phys<T>& P = R.P;
+    const GBL double* Qe = R.Q + e * 9 * N3;
+    const GBL double* Se = R.S_fp + e * 9 * NF;
+    const GBL int32_t* nb6 = R.nbr + e * 6;
     const bool use_kr = P.kr_scale != T(0);
 
     // A. every global read of this element is issued here: the state into
@@ -303,20 +384,20 @@ void k_volume(Launch L) {
     for (int i = tid; i < 9 * N3; i += BS) sQ[i] = (T)Qe[i];
     T ji = T(0), Sj[3][3], xs[3] = {T(0), T(0), T(0)};
     if (tid < N3) {
-      ji = T(1) / (T)rd->detJ[e * N3 + tid];
+      ji = T(1) / (T)R.detJ[e * N3 + tid];
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Sj[d][c] = (T)rd->Sj_sp[(e * 9 + d * 3 + c) * N3 + tid];
+        for (int c = 0; c < 3; ++c) Sj[d][c] = (T)R.Sj_sp[(e * 9 + d * 3 + c) * N3 + tid];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) xs[c] = (T)rd->x_sp[(e * 3 + c) * N3 + tid];
+      for (int c = 0; c < 3; ++c) xs[c] = (T)R.x_sp[(e * 3 + c) * N3 + tid];
     }
     T fq[9], fn[3];  // face point: outside state (neighbour trace or ghost), normal
     int32_t fcode = 0;
     if (FACE_REG && tid < 6 * N2) {
       const int f = tid / N2, ab = tid % N2;
       fcode = nb6[f];
-      load_outside<N>(rd, e, f, ab, fcode, Qtr, P, fq, fn);
+      load_outside<N>(R, f, ab, fcode, fq, fn);
     }
     T Sint[3][3];  // metric at the interior flux point `tid` of each family
     if (!DIAG && INT_REG && tid < NI) {
@@ -338,7 +419,7 @@ void k_volume(Launch L) {
       const int ab = it % N2, fv = it / N2, v = fv % 9, f = fv / 9;
       const int d = f >> 1;
       const int st = d == 0 ? 1 : (d == 1 ? N : N2);
-      sTr[it] = line_interp<N>(sQ + v * N3, tb.I[(f & 1) ? N : 0], sp_line<N>(d, ab % N, ab / N, 0), st);
+      sTr[it] = line_interp<N>(sQ + v * N3, sI + ((f & 1) ? N : 0) * N, sp_line<N>(d, ab % N, ab / N, 0), st);
     }
     __syncthreads();
     //    B2: jumps from the own and the outside (neighbour, wall or ghost) state
@@ -353,7 +434,7 @@ void k_volume(Launch L) {
         n[0] = fn[0]; n[1] = fn[1]; n[2] = fn[2];
       } else {
         code = nb6[f];
-        load_outside<N>(rd, e, f, ab, code, Qtr, P, q_out, n);
+        load_outside<N>(R, f, ab, code, q_out, n);
       }
       const T* own = sTr + f * 9 * N2 + ab;
       T* dst = sU + f * 9 * N2 + ab;
@@ -415,8 +496,8 @@ void k_volume(Launch L) {
       double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       if (tid < N3) {
         const int sp = tid;
-        const double wq = (double)tb.W[ia0] * (double)tb.W[ia1] * (double)tb.W[ia2] * rd->detJ[e * N3 + sp];
-        const double* q = Qe + sp;
+        const double wq = (double)tb.W[ia0] * (double)tb.W[ia1] * (double)tb.W[ia2] * R.detJ[e * N3 + sp];
+        const GBL double* q = Qe + sp;
         const double rho = q[0];
         const double m2 = q[N3] * q[N3] + q[2 * N3] * q[2 * N3] + q[3 * N3] * q[3 * N3];
         const double b2 = q[5 * N3] * q[5 * N3] + q[6 * N3] * q[6 * N3] + q[7 * N3] * q[7 * N3];
@@ -448,11 +529,11 @@ void k_volume(Launch L) {
         for (int wv = 0; wv < BS / 64; ++wv)
           for (int k = 0; k < 9; ++k)
             out[k] = (k == 5 || k == 7 || k == 8) ? fmax(out[k], sRed[wv][k]) : out[k] + sRed[wv][k];
-        double* dst = (double*)rd->Rp + e * 10;
+        GBL double* dst = (GBL double*)R.Rp + e * 10;
         for (int k = 0; k < 10; ++k) dst[k] = out[k];
       }
       __syncthreads();
-      continue;
+      return;
     }
 
     // D. fluxes and their divergence.
@@ -462,7 +543,6 @@ void k_volume(Launch L) {
     T div[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v) div[v] = T(0);
-    T* Vtr = (T*)rd->Vtr;
 #pragma unroll 1
     for (int it = tid; it < 6 * N2; it += BS) {
       const int face = it / N2, ab = it % N2, p = ab % N, q = ab / N;
@@ -470,7 +550,7 @@ void k_volume(Launch L) {
       const int st = d == 0 ? 1 : (d == 1 ? N : N2);
       const int s0 = sp_line<N>(d, p, q, 0);
       T qf[9], gf[27];
-      T kf = interp_point<N>(sQ, sG, tb.I[fe], s0, st, qf, gf, use_kr, rd, e, P);
+      T kf = interp_point<N>(sQ, sG, sI + fe * N, s0, st, qf, gf, use_kr, R);
       T qx[9], n[3];
       int32_t code;
       if (FACE_REG) {
@@ -480,7 +560,7 @@ void k_volume(Launch L) {
         n[0] = fn[0]; n[1] = fn[1]; n[2] = fn[2];
       } else {
         code = nb6[face];
-        load_outside<N>(rd, e, face, ab, code, Qtr, P, qx, n);
+        load_outside<N>(R, face, ab, code, qx, n);
       }
       T F[9];
       ViscLocal<T> vl;
@@ -490,7 +570,7 @@ void k_volume(Launch L) {
         viscous_local(qf, gf, kf, P, vl);
         T Fv[7];
         flux_viscous7(vl, n, P, Fv);
-        T* vt = Vtr + (e * 6 + face) * 7 * N2 + ab;
+        GBL T* vt = R.Vtr + (e * 6 + face) * 7 * N2 + ab;
 #pragma unroll
         for (int c = 0; c < 7; ++c) vt[c * N2] = Fv[c];
         rusanov(qf, qx, n, P, F);
@@ -531,7 +611,7 @@ void k_volume(Launch L) {
       for (int d = 0; d < 3; ++d) {
         const int p = d == 0 ? ia1 : ia0, q = d == 2 ? ia1 : ia2, i = d == 0 ? ia0 : (d == 1 ? ia1 : ia2);
         const int pq = p + N * q;
-        const T d0 = tb.D[i][0], dN = tb.D[i][N];
+        const T d0 = sD[i * NP], dN = sD[i * NP + N];
 #pragma unroll
         for (int v = 0; v < 9; ++v)
           div[v] += d0 * sU[((2 * d) * 9 + v) * N2 + pq] + dN * sU[((2 * d + 1) * 9 + v) * N2 + pq];
@@ -547,7 +627,7 @@ void k_volume(Launch L) {
         const int p = line % N, q = line / N;
         const int s0 = sp_line<N>(d, p, q, 0);
         T qf[9], gf[27];
-        T kf = interp_point<N>(sQ, sG, tb.I[f], s0, st, qf, gf, use_kr, rd, e, P);
+        T kf = interp_point<N>(sQ, sG, sI + f * N, s0, st, qf, gf, use_kr, R);
         T Sd[3];
         if (INT_REG) {
           Sd[0] = Sint[d][0]; Sd[1] = Sint[d][1]; Sd[2] = Sint[d][2];
@@ -572,7 +652,7 @@ void k_volume(Launch L) {
         const int base = (p + N * q) * (N - 1);
 #pragma unroll 1
         for (int f = 1; f < N; ++f) {
-          const T df = tb.D[i][f];
+          const T df = sD[i * NP + f];
 #pragma unroll
           for (int v = 0; v < 9; ++v) div[v] += df * sU[v * NI + base + f - 1];
         }
@@ -605,7 +685,7 @@ void k_volume(Launch L) {
       M[6] = -db * q[2] * ir;
       M[7] = -db * q[3] * ir;
       M[8] = -P.glm_a * q[8];
-      T* rp = (T*)rd->Rp + e * 9 * N3 + sp;
+      GBL T* rp = R.Rp + e * 9 * N3 + sp;
 #pragma unroll
       for (int v = 0; v < 9; ++v) rp[v * N3] = M[v] - div[v] * ji;
     }
@@ -621,15 +701,17 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
   constexpr int N2 = N * N, N3 = N2 * N, NP = N + 1, BS = block_threads<N>();
   __shared__ T sV[6 * 7 * N2];
   __shared__ double sOut[STAGE ? 9 * N3 : 1];
-  const DevTab<T>& tb = tab<T>(N);
-  const DevTab<double>& tbd = tab<double>(N);
+  __shared__ T sI[(N + 1) * N], sD[N * (N + 1)];
   const int tid = threadIdx.x;
-  for (int64_t w = blockIdx.x; w < L.n_work; w += gridDim.x) {
-    const RunDesc* rd;
-    int64_t e;
-    locate(L, w, rd, e);
-    const int32_t* nb6 = rd->nbr + e * 6;
-    const T* Vtr = (const T*)rd->Vtr;
+  stage_tables<N>(sI, sD);
+  {
+    // one element per workgroup; no loop, so nothing per element is kept
+    // live across elements
+    const int64_t w = L.w0 + blockIdx.x;
+    if (w >= L.n_work) return;
+    const Run<T> R = view<T>(L, w);
+    const int64_t e = R.e;
+    const GBL int32_t* nb6 = R.nbr + e * 6;
     for (int it = tid; it < 6 * N2; it += BS) {
       const int f = it / N2, ab = it % N2;
       const int32_t code = nb6[f];
@@ -638,7 +720,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
         const int fn = (code >> 3) & 7, o = code & 7;
         int a2, b2;
         omap<N>(o, ab % N, ab / N, a2, b2);
-        const T* src = Vtr + (en * 6 + fn) * 7 * N2 + a2 + N * b2;
+        const GBL T* src = R.Vtr + (en * 6 + fn) * 7 * N2 + a2 + N * b2;
 #pragma unroll
         for (int c = 0; c < 7; ++c) sV[(f * 7 + c) * N2 + ab] = src[c * N2];
       } else {
@@ -649,63 +731,72 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
     __syncthreads();
     for (int sp = tid; sp < N3; sp += BS) {
       const int ia[3] = {sp % N, (sp / N) % N, sp / N2};
+      // this SP's own-element inputs are requested before the gather below
+      const T ji = T(1) / (T)R.detJ[e * N3 + sp];
+      const GBL T* rp = R.Rp + e * 9 * N3 + sp;
+      T rpv[9];
+#pragma unroll
+      for (int v = 0; v < 9; ++v) rpv[v] = rp[v * N3];
+      double u[9];
+      if (STAGE) {
+        // Shu-Osher stage in FP64: sum_k alpha_k u_k + beta dt R; the
+        // register reads do not depend on each other
+#pragma unroll
+        for (int v = 0; v < 9; ++v) u[v] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (k < R.n_in) {
+            const double a = R.alpha[k];
+            const GBL double* src = R.in[k] + e * 9 * N3 + sp;
+#pragma unroll
+            for (int v = 0; v < 9; ++v) u[v] += a * src[v * N3];
+          }
+        }
+      }
       T corr[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const int p = d == 0 ? ia[1] : ia[0], q = d == 2 ? ia[1] : ia[2], i = ia[d];
         const int pq = p + N * q;
-        const T w0 = T(-0.5) * tb.D[i][0], wN = T(0.5) * tb.D[i][N];
+        const T w0 = T(-0.5) * sD[i * NP], wN = T(0.5) * sD[i * NP + N];
 #pragma unroll
         for (int c = 0; c < 7; ++c)
           corr[c] += w0 * sV[((2 * d) * 7 + c) * N2 + pq] + wN * sV[((2 * d + 1) * 7 + c) * N2 + pq];
       }
-      const T ji = T(1) / (T)rd->detJ[e * N3 + sp];
-      const T* rp = (const T*)rd->Rp + e * 9 * N3 + sp;
       double Rv[9];
 #pragma unroll
       for (int v = 0; v < 9; ++v) {
         const T c = (v >= 1 && v <= 7) ? corr[v - 1] : T(0);
-        Rv[v] = (double)(rp[v * N3] - c * ji);
+        Rv[v] = (double)(rpv[v] - c * ji);
       }
       if (!STAGE) {
-        double* R = rd->R + e * 9 * N3 + sp;
+        GBL double* Ro = R.R + e * 9 * N3 + sp;
 #pragma unroll
-        for (int v = 0; v < 9; ++v) R[v * N3] = Rv[v];
+        for (int v = 0; v < 9; ++v) Ro[v * N3] = Rv[v];
       } else {
-        // Shu-Osher stage in FP64: sum_k alpha_k u_k + beta dt R
-        double u[9];
 #pragma unroll
-        for (int v = 0; v < 9; ++v) u[v] = rd->beta_dt * Rv[v];
-        for (int k = 0; k < rd->n_in; ++k) {
-          const double a = rd->alpha[k];
-          const double* src = rd->in[k] + e * 9 * N3 + sp;
-#pragma unroll
-          for (int v = 0; v < 9; ++v) u[v] += a * src[v * N3];
-        }
-#pragma unroll
-        for (int v = 0; v < 9; ++v) sOut[v * N3 + sp] = u[v];
+        for (int v = 0; v < 9; ++v) sOut[v * N3 + sp] = u[v] + R.beta_dt * Rv[v];
       }
     }
     if (STAGE) {
       __syncthreads();
-      double* out = rd->out + e * 9 * N3;
+      GBL double* out = R.out + e * 9 * N3;
       for (int i = tid; i < 9 * N3; i += BS) out[i] = sOut[i];
-      if (rd->write_traces) {
-        T* tr = (T*)rd->Qtr + e * 6 * 9 * N2;
+      if (R.write_traces) {
+        GBL T* tr = R.Qtr + e * 6 * 9 * N2;
         for (int it = tid; it < 6 * 9 * N2; it += BS) {
           const int ab = it % N2, fv = it / N2, v = fv % 9, f = fv / 9;
-          const int d = f >> 1, fe = (f & 1) ? N : 0;
+          const int d = f >> 1;
+          const T* wI = sI + ((f & 1) ? N : 0) * N;
           T s = T(0);
 #pragma unroll
-          for (int i = 0; i < N; ++i) s += tb.I[fe][i] * (T)sOut[v * N3 + sp_line<N>(d, ab % N, ab / N, i)];
+          for (int i = 0; i < N; ++i) s += wI[i] * (T)sOut[v * N3 + sp_line<N>(d, ab % N, ab / N, i)];
           tr[it] = s;
         }
       }
-      (void)tbd;
     }
     __syncthreads();
   }
-  (void)NP;
 }
 
 // ---------------------------------------------------------------------------
@@ -894,17 +985,24 @@ RunDesc make_desc(const sdm_ctx* c, const sdm_params* p, const double* Q, void* 
 template <int N, typename T>
 hipError_t launch_all(int which, const Launch& L, hipStream_t s, int64_t cap) {
   constexpr int BS = block_threads<N>();
-  const unsigned grid = (unsigned)std::min<int64_t>(std::min<int64_t>(L.n_work, cap), (int64_t)1 << 30);
-  if (L.n_work == 0) return hipSuccess;
-  switch (which) {
-    case 0: hipLaunchKernelGGL((k_traces<N, T>), dim3(grid), dim3(BS), 0, s, L); break;
-    case 1: hipLaunchKernelGGL((k_volume<N, T, false>), dim3(grid), dim3(BS), 0, s, L); break;
-    case 2: hipLaunchKernelGGL((k_volume<N, T, true>), dim3(grid), dim3(BS), 0, s, L); break;
-    case 3: hipLaunchKernelGGL((k_finish<N, T, false>), dim3(grid), dim3(BS), 0, s, L); break;
-    case 4: hipLaunchKernelGGL((k_finish<N, T, true>), dim3(grid), dim3(BS), 0, s, L); break;
-    default: return hipErrorInvalidValue;
+  // at most `cap` workgroups per launch: consecutive launches cover the work
+  const int64_t step = std::min<int64_t>(cap, (int64_t)1 << 30);
+  for (int64_t w0 = 0; w0 < L.n_work; w0 += step) {
+    Launch Lc = L;
+    Lc.w0 = w0;
+    const unsigned grid = (unsigned)std::min<int64_t>(L.n_work - w0, step);
+    switch (which) {
+      case 0: hipLaunchKernelGGL((k_traces<N, T>), dim3(grid), dim3(BS), 0, s, Lc); break;
+      case 1: hipLaunchKernelGGL((k_volume<N, T, false>), dim3(grid), dim3(BS), 0, s, Lc); break;
+      case 2: hipLaunchKernelGGL((k_volume<N, T, true>), dim3(grid), dim3(BS), 0, s, Lc); break;
+      case 3: hipLaunchKernelGGL((k_finish<N, T, false>), dim3(grid), dim3(BS), 0, s, Lc); break;
+      case 4: hipLaunchKernelGGL((k_finish<N, T, true>), dim3(grid), dim3(BS), 0, s, Lc); break;
+      default: return hipErrorInvalidValue;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 template <typename T>
