@@ -11,6 +11,9 @@
       kernel, which reads B and writes B bytes), so the figure is in the
       units of bytes actually moved.  Appends an entry to OUT (JSON) and
       prints a markdown summary.
+  python -m paper_2502_17805_amd.rocprof_summary counters DIR [DIR ...]
+      every counter of every kernel of this library in one or more --pmc
+      runs, means per dispatch, as a markdown table.
 
 Reads the SQLite databases rocprofv3 writes (tables `top_kernels`, `kernels`,
 `pmc_events`).
@@ -44,27 +47,48 @@ def trace_table(path, title, cmd, limit=16):
                        "workgroup_x, grid_x from kernels group by name"):
         res[r[0]] = r[1:]
     out = [f"# {title}", "", "Command (from the repository root):", "", "```", cmd, "```", "",
-           "| kernel | calls | total us | avg us | % | VGPR | AGPR | LDS B | scratch B | wg | grid |",
+           "| kernel | calls | total us | avg us | % | VGPR* | AGPR | LDS B | scratch B | wg | grid threads |",
            "|---|---|---|---|---|---|---|---|---|---|---|"]
     for n, calls, tot, avg, pct in rows:
         v = res.get(n, (None,) * 7)
-        out.append(f"| `{n[:80]}` | {calls} | {tot / 1e3:.0f} | {avg / 1e3:.1f} | {pct:.1f} | {v[0]} | {v[1]} | "
+        out.append(f"| `{n[:80]}` | {calls} | {tot:.0f} | {avg:.1f} | {pct:.1f} | {v[0]} | {v[1]} | "
                    f"{v[3]} | {v[4]} | {v[5]} | {v[6]} |")
+    out += ["", "*VGPR as recorded by the profiler (allocation granules may differ from the compiler's count)."]
     return "\n".join(out) + "\n"
 
 
 def pmc_per_kernel(path):
-    """{kernel name: {counter: mean per dispatch}}; a counter reported per
-    hardware instance is summed over instances within each dispatch."""
+    """{kernel name: {counter: mean per dispatch}} (plus "duration_ns"); a
+    counter reported per hardware instance is summed over instances within
+    each dispatch."""
     c = sqlite3.connect(_db(path))
     per = collections.defaultdict(lambda: collections.defaultdict(float))
-    for name, disp, cn, v in c.execute("select name, dispatch_id, counter_name, counter_value from pmc_events"):
+    for name, disp, cn, v, dur in c.execute("select name, dispatch_id, counter_name, counter_value, duration "
+                                            "from pmc_events"):
         per[(name, disp)][cn] += v
+        per[(name, disp)]["duration_ns"] = dur
     agg = collections.defaultdict(lambda: collections.defaultdict(list))
     for (name, _), cs in per.items():
         for cn, v in cs.items():
             agg[name][cn].append(v)
     return {n: {cn: sum(v) / len(v) for cn, v in cs.items()} for n, cs in agg.items()}
+
+
+def counter_table(dirs, sub="sdm::k_"):
+    """Markdown table of every counter of every kernel matching `sub`, over
+    one or more --pmc runs of the same program (means per dispatch)."""
+    merged = collections.defaultdict(dict)
+    for d in dirs:
+        for n, cs in pmc_per_kernel(d).items():
+            if sub in n:
+                merged[n].update(cs)
+    names = sorted({cn for cs in merged.values() for cn in cs if cn != "duration_ns"})
+    out = ["| kernel | avg us | " + " | ".join(names) + " |", "|---" * (len(names) + 2) + "|"]
+    for n, cs in merged.items():
+        short = n.split("(")[0].replace("void ", "")
+        out.append(f"| `{short}` | {cs.get('duration_ns', 0) / 1e3:.0f} | " +
+                   " | ".join(f"{cs[c]:.4g}" if c in cs else "" for c in names) + " |")
+    return "\n".join(out) + "\n"
 
 
 def _pick(table, sub):
@@ -76,9 +100,10 @@ def _pick(table, sub):
 
 def traffic(fetch_dir, write_dir, copy_bytes, kernel_sub):
     fe, wr = pmc_per_kernel(fetch_dir), pmc_per_kernel(write_dir)
-    copy_sub = "elementwise_kernel"
-    cf = max(fe[n]["FETCH_SIZE"] for n in _pick(fe, copy_sub))  # the big copy dominates
-    cw = max(wr[n]["WRITE_SIZE"] for n in _pick(wr, copy_sub))
+    # the copy: the elementwise kernel that fetches the most (the fills that
+    # initialise buffers fetch nothing)
+    copy = max(_pick(fe, "elementwise_kernel"), key=lambda n: fe[n]["FETCH_SIZE"])
+    cf, cw = fe[copy]["FETCH_SIZE"], wr[copy]["WRITE_SIZE"]
     kf = {n: fe[n]["FETCH_SIZE"] for n in _pick(fe, kernel_sub)}
     kw = {n: wr[n]["WRITE_SIZE"] for n in _pick(wr, kernel_sub)}
     name = max(kf, key=kf.get)
@@ -94,6 +119,9 @@ def main(argv=None):
     t.add_argument("dir")
     t.add_argument("--title", required=True)
     t.add_argument("--cmd", required=True)
+    k = sub.add_parser("counters")
+    k.add_argument("dirs", nargs="+")
+    k.add_argument("--kernel", default="sdm::k_")
     f = sub.add_parser("traffic")
     f.add_argument("--fetch", required=True)
     f.add_argument("--write", required=True)
@@ -106,6 +134,9 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd_name == "trace":
         sys.stdout.write(trace_table(a.dir, a.title, a.cmd))
+        return
+    if a.cmd_name == "counters":
+        sys.stdout.write(counter_table(a.dirs, a.kernel))
         return
     r = traffic(a.fetch, a.write, a.copy_bytes, a.kernel)
     r["source_hash"] = a.source_hash
