@@ -28,6 +28,11 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2502_17805_amd/build.py "
                       "(or __graft_entry__.build()) first -- there is no fallback path")
 
+# torch is loaded first so that the library binds to the same HIP runtime
+# (by soname) as the torch that allocates its memory and streams; two HIP
+# runtimes in one process do not share devices.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 SDM_OK = 0

@@ -67,11 +67,16 @@ class _MeshCache:
         self.dev = {}
         self.users = collections.Counter()
 
-    def get(self, Nz, Nr, p):
-        import torch
+    def host_mesh(self, Nz, Nr, p):
         key = (Nz, Nr, p)
         if key not in self.host:
             self.host[key] = sd.shell(Nz, Nr, p)
+        return self.host[key]
+
+    def get(self, Nz, Nr, p):
+        import torch
+        key = (Nz, Nr, p)
+        self.host_mesh(Nz, Nr, p)
         if key not in self.dev:
             m = self.host[key]
             t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(self.device)  # noqa: E731
@@ -103,10 +108,21 @@ def request_bytes(q: Request) -> int:
     return 4 * 8 * 9 * q.dof + ws + _MeshCache.device_bytes(q.Nz, q.Nr, q.p)
 
 
+def prepare(req: Request, mesh):
+    """The request's input: seeded initial state, physical parameters and
+    time step (synthesised on the host; a client would send them)."""
+    bg = inp.Background(req.N_rho)
+    Q = inp.shell_state(mesh.x_sp, bg, req.seed)
+    pr = inp.run_params(req.seed, bg)
+    ch = inp.glm_speed(Q)
+    pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
+    return Q, pr, inp.time_step(Q, mesh.Sj_sp, ch, 0.1)
+
+
 class _Run:
     """One admitted request resident on the device."""
 
-    def __init__(self, req: Request, cache: _MeshCache, device, t_admit):
+    def __init__(self, req: Request, cache: _MeshCache, device, t_admit, prepared=None):
         import torch
         self.req = req
         self.t_admit = t_admit
@@ -121,13 +137,8 @@ class _Run:
         nb = C.c_size_t()
         sd._check(sd._lib.sdm_workspace_size(h, C.byref(nb)))
         self.ws = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
-        bg = inp.Background(req.N_rho)
-        Q = inp.shell_state(mesh.x_sp, bg, req.seed)
-        pr = inp.run_params(req.seed, bg)
-        ch = inp.glm_speed(Q)
-        pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
+        Q, pr, self.dt = prepared if prepared is not None else prepare(req, mesh)
         self.prm = sd.make_params(**pr)
-        self.dt = inp.time_step(Q, mesh.Sj_sp, ch, 0.1)
         shp = (mesh.E, 9, mesh.N ** 3)
         self.regs = [torch.empty(shp, dtype=torch.float64, device=device) for _ in range(4)]
         self.regs[0].copy_(torch.from_numpy(Q))
@@ -156,7 +167,9 @@ class Server:
     """Admission by slots and HBM budget; one batched SSPRK step per iteration."""
 
     def __init__(self, budget_bytes: float = 200e9, max_slots: int = 64, device: int = 0, max_blocks: int = 0,
-                 keep_states: bool = False):
+                 keep_states=False):
+        """keep_states: True (all), a set of request ids, or False: whose
+        final states are copied back with their results."""
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -187,11 +200,20 @@ class Server:
         for r in active:
             r.steps_done += 1
 
-    def run(self, requests):
+    def run(self, requests, prepare_inputs: bool = True):
+        """Serve the requests (arrival times relative to the start).  With
+        prepare_inputs the requests' inputs and meshes are made on the host
+        before the clock starts, so the latencies measure the GPU service."""
         torch = self.torch
         pending = collections.deque(sorted(requests, key=lambda q: q.arrival))
+        prepared = {}
+        if prepare_inputs:
+            for q in pending:
+                m = self.cache.host_mesh(q.Nz, q.Nr, q.p)
+                prepared[q.rid] = prepare(q, m)
         active, results = [], []
         used, peak_used, peak_active, iters, queued_wait = 0, 0, 0, 0, 0
+        torch.cuda.synchronize(self.device)
         t0 = time.perf_counter()
         while pending or active:
             now = time.perf_counter() - t0
@@ -201,7 +223,7 @@ class Server:
                     queued_wait += 1
                     break
                 pending.popleft()
-                r = _Run(q, self.cache, self.device, time.perf_counter() - t0)
+                r = _Run(q, self.cache, self.device, time.perf_counter() - t0, prepared.pop(q.rid, None))
                 used += r.bytes
                 active.append(r)
             peak_used = max(peak_used, used)
@@ -217,12 +239,12 @@ class Server:
             still = []
             for r in active:
                 if r.steps_done >= r.req.steps:
-                    diag = np.zeros(16)
                     out = torch.zeros(16, dtype=torch.float64, device=self.device)
                     sd._check(sd._lib.sdm_diagnostics(r.ctx, C.byref(r.prm), r.regs[0].data_ptr(), out.data_ptr(),
                                                       r.ws.data_ptr(), self._stream()))
                     diag = out.cpu().numpy()
-                    state = r.regs[0].cpu().numpy() if self.keep_states else None
+                    keep = self.keep_states is True or (self.keep_states and r.req.rid in self.keep_states)
+                    state = r.regs[0].cpu().numpy() if keep else None
                     results.append(Result(r.req.rid, r.req.arrival, r.t_admit, tnow, r.steps_done, r.req.dof,
                                           diag, state))
                     used -= r.bytes
@@ -253,3 +275,37 @@ def poisson_requests(n: int = 64, mean_gap_s: float = 0.020, steps: int = 500, s
         out.append(Request(i, int(Nz), int(Nr), int(degrees[rng.integers(len(degrees))]),
                            float(n_rhos[rng.integers(len(n_rhos))]), 1000 + i, steps, arith, t))
     return out
+
+
+def main(argv=None):
+    """Serve the Poisson ensemble once and print one JSON line: latency
+    percentiles, aggregate DOF x RK-stage throughput, admission figures, and
+    the bitwise alone-vs-mixed check of the first `--identity` requests."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--arith", type=int, default=0)
+    ap.add_argument("--mean-gap", type=float, default=0.020)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--identity", type=int, default=3)
+    a = ap.parse_args(argv)
+    reqs = poisson_requests(a.requests, a.mean_gap, a.steps, arith=a.arith)
+    ids = set(range(min(a.identity, len(reqs))))
+    srv = Server(budget_bytes=a.budget_gb * 1e9, max_slots=a.slots, keep_states=ids)
+    res, st = srv.run(reqs)
+    same = []
+    for i in sorted(ids):
+        alone, _ = Server(max_slots=1, keep_states=True).run([dataclasses.replace(reqs[i], arrival=0.0)])
+        same.append(bool(np.array_equal(alone[0].state, res[i].state)))
+    out = dict(workload=f"{a.requests} requests, Poisson arrivals (mean gap {a.mean_gap * 1e3:g} ms), shells "
+                        f"6x{{4,8,12}}^2x{{3,4,8}}, p in {{3,5}}, N_rho in {{3,5}}, {a.steps} SSPRK(5,3) steps each",
+               arith="fp64" if a.arith == 0 else "fp32-mixed", budget_gb=a.budget_gb, slots=a.slots,
+               nan_results=int(sum(r.diag[8] != 0 for r in res)), alone_vs_mix_bitwise=same, **st)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -34,7 +34,8 @@ def test_alone_equals_mix(srv):
 
 
 def test_forced_queueing_same_results(srv):
-    reqs = _reqs(srv)
+    import dataclasses
+    reqs = [dataclasses.replace(q, arrival=0.0) for q in _reqs(srv)]
     budget = max(srv.request_bytes(q) for q in reqs) * 1.01  # the largest fits, not all together
     queued, st = srv.Server(budget_bytes=budget, max_slots=8, keep_states=True).run(reqs)
     assert st["admissions_deferred"] > 0 and st["peak_active"] < len(reqs)
