@@ -389,7 +389,15 @@ static int build_faces(or_mesh* m, const int32_t* ckey) {
 static void element_metrics(or_mesh* m, int64_t e) {
   const tab_t* t = &m->t;
   const int N = t->N, NP = N + 1, N3 = N * N * N, NPn = NP * NP * NP, NF = NP * N * N;
-  const double* X = &m->xn[e * 3 * NPn];
+  const double* Xa = &m->xn[e * 3 * NPn];
+  /* The metric terms, the map derivatives and |J| do not change when the
+   * element is translated (the discrete curl of a discrete gradient is zero
+   * for tensor-product polynomials), so they are formed from the node
+   * positions relative to the element's first node: with coordinates of
+   * size h instead of 1 their round-off scales like the terms themselves. */
+  double* X = (double*)malloc(sizeof(double) * 3 * NPn);
+  for (int c = 0; c < 3; ++c)
+    for (int q = 0; q < NPn; ++q) X[c * NPn + q] = Xa[c * NPn + q] - Xa[c * NPn];
   double Dn[(OR_NMAX + 1) * (OR_NMAX + 1)];
   for (int g = 0; g < NP; ++g)
     for (int f = 0; f < NP; ++f) Dn[g * NP + f] = t->Dn[g][f];
@@ -436,7 +444,7 @@ static void element_metrics(or_mesh* m, int64_t e) {
   }
   /* positions and Jacobian determinant at the solution points */
   int opL[3] = {OP_L, OP_L, OP_L};
-  for (int c = 0; c < 3; ++c) eval_nodes(t, &X[c * NPn], opL, &m->xsp[(e * 3 + c) * N3]);
+  for (int c = 0; c < 3; ++c) eval_nodes(t, &Xa[c * NPn], opL, &m->xsp[(e * 3 + c) * N3]);
   double* Jm = (double*)malloc(sizeof(double) * 9 * N3); /* Jm[c][k] = dx_c/dxi_k */
   for (int k = 0; k < 3; ++k) {
     int op[3] = {OP_L, OP_L, OP_L};
@@ -451,7 +459,7 @@ static void element_metrics(or_mesh* m, int64_t e) {
                           a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
                           a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
   }
-  free(Jm); free(dX); free(Wn); free(tmp);
+  free(Jm); free(dX); free(Wn); free(tmp); free(X);
 }
 
 static or_mesh* mesh_alloc(int N, int64_t E) {

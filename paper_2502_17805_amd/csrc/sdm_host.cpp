@@ -187,9 +187,19 @@ Block3 sample(const Tables1D& t, const Block3& nodes, Op o0, Op o1, Op o2) {
 
 // Metric data of one element from the map nodes X[c] (c = x, y, z) on the
 // (N+1)^3 flux-point tensor grid.
-void element_geometry(const Tables1D& t, const Block3 X[3], double* x_sp, double* detJ,
+void element_geometry(const Tables1D& t, const Block3 Xabs[3], double* x_sp, double* detJ,
                       double* S_fp, double* S_sp) {
   const int N = t.N, NP = N + 1, N3 = N * N * N, NF = NP * N * N;
+  // The metric terms, the map derivatives and |J| are invariant under a
+  // translation of the element (the discrete curl of a discrete gradient of
+  // a tensor-product polynomial vanishes), so they are formed from node
+  // positions relative to the element's first node: coordinates of size h
+  // instead of 1 keep their round-off proportional to the terms (h^2).
+  Block3 X[3] = {Xabs[0], Xabs[1], Xabs[2]};
+  for (int c = 0; c < 3; ++c) {
+    const double o = Xabs[c].v[0];
+    for (double& v : X[c].v) v -= o;
+  }
   // derivatives of the map at the nodes
   Block3 dX[3][3] = {{X[0], X[0], X[0]}, {X[0], X[0], X[0]}, {X[0], X[0], X[0]}};  // [axis][comp]
   for (int ax = 0; ax < 3; ++ax)
@@ -224,7 +234,7 @@ void element_geometry(const Tables1D& t, const Block3 X[3], double* x_sp, double
   // positions and Jacobian determinant at the solution points
   Block3 J[3][3] = {{X[0], X[0], X[0]}, {X[0], X[0], X[0]}, {X[0], X[0], X[0]}};  // J[c][axis]
   for (int c = 0; c < 3; ++c) {
-    Block3 p = sample(t, X[c], VAL, VAL, VAL);
+    Block3 p = sample(t, Xabs[c], VAL, VAL, VAL);
     std::memcpy(x_sp + c * N3, p.v.data(), sizeof(double) * N3);
     J[c][0] = sample(t, X[c], DER, VAL, VAL);
     J[c][1] = sample(t, X[c], VAL, DER, VAL);
