@@ -210,6 +210,17 @@ constexpr int block_threads() {
   return ((N * N * N + 63) / 64) * 64 < 64 ? 64 : ((N * N * N + 63) / 64) * 64;
 }
 
+// Position of solution point x inside an LDS field block of k_volume.  For
+// even N the two doubles of each pair swap places when bit 4 of x is set:
+// the accesses at a stride of N = 6 doubles (lines along the first
+// reference direction, read across consecutive lanes) then fall in 16
+// distinct 8-byte bank pairs instead of 8.
+template <int N>
+__device__ __forceinline__ int swz(int x) {
+  if constexpr ((N & 1) == 0) return x ^ ((x >> 4) & 1);
+  return x;
+}
+
 // ---------------------------------------------------------------------------
 // interpolation of one solution-point field along a line to one flux point
 // ---------------------------------------------------------------------------
@@ -217,7 +228,7 @@ template <int N, typename T>
 __device__ __forceinline__ T line_interp(const T* f, const T* w, int s0, int st) {
   T s = T(0);
 #pragma unroll
-  for (int i = 0; i < N; ++i) s += w[i] * f[s0 + i * st];
+  for (int i = 0; i < N; ++i) s += w[i] * f[swz<N>(s0 + i * st)];
   return s;
 }
 
@@ -236,11 +247,11 @@ __device__ __forceinline__ T interp_point(const T* sQ, const T* sG, const T* w, 
 #pragma unroll 1
   for (int i = 0; i < N; ++i) {
     const T wi = w[i];
-    const int sidx = s0 + i * st;
+    const int sidx = s0 + i * st, lidx = swz<N>(sidx);
 #pragma unroll
-    for (int v = 0; v < 9; ++v) qf[v] += wi * sQ[v * N3 + sidx];
+    for (int v = 0; v < 9; ++v) qf[v] += wi * sQ[v * N3 + lidx];
 #pragma unroll
-    for (int k = 0; k < 27; ++k) gf[k] += wi * sG[k * N3 + sidx];
+    for (int k = 0; k < 27; ++k) gf[k] += wi * sG[k * N3 + lidx];
     if (use_kr) {
       const T x[3] = {(T)R.x_sp[(R.e * 3 + 0) * N3 + sidx], (T)R.x_sp[(R.e * 3 + 1) * N3 + sidx],
                       (T)R.x_sp[(R.e * 3 + 2) * N3 + sidx]};
@@ -362,7 +373,6 @@ void k_volume(Launch L) {
   const DevTab<T>& tb = tab<T>(N);
   const int tid = threadIdx.x;
   const int ia0 = tid % N, ia1 = (tid / N) % N, ia2 = tid / N2;  // this thread's SP (tid < N3)
-  stage_tables<N>(sI, sD);
 
   {
     // one element per workgroup; no loop, so nothing per element is kept
@@ -381,10 +391,10 @@ void k_volume(Launch L) {
     //    LDS; the chain-rule factors and position of this thread's SP; the
     //    outside state and normal of this thread's face point; the metric at
     //    this thread's interior flux points of the three families.
-    for (int i = tid; i < 9 * N3; i += BS) sQ[i] = (T)Qe[i];
+    for (int i = tid; i < 9 * N3; i += BS) sQ[i - i % N3 + swz<N>(i % N3)] = (T)Qe[i];
     T ji = T(0), Sj[3][3], xs[3] = {T(0), T(0), T(0)};
     if (tid < N3) {
-      ji = T(1) / (T)R.detJ[e * N3 + tid];
+      ji = recip((T)R.detJ[e * N3 + tid]);
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -409,6 +419,7 @@ void k_volume(Launch L) {
         for (int c = 0; c < 3; ++c) Sint[d][c] = (T)Se[(d * 3 + c) * NF + fi];
       }
     }
+    stage_tables<N>(sI, sD);  // after the element's loads are in flight
     __syncthreads();
 
     // B. BR1 common solution at the 6 N^2 face points, stored as the jump
@@ -446,7 +457,7 @@ void k_volume(Launch L) {
         T qo[9], qc[9];
 #pragma unroll
         for (int v = 0; v < 9; ++v) qo[v] = own[v * N2];
-        const T inn = T(1) / sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        const T inn = recip(sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]));
         const T nh[3] = {n[0] * inn, n[1] * inn, n[2] * inn};
         wall_common(qo, nh, g, P, qc);
 #pragma unroll
@@ -466,15 +477,15 @@ void k_volume(Launch L) {
       const int s0 = sp_line<N>(d, pq % N, pq / N, 0);
       T ln[N];
 #pragma unroll
-      for (int j = 0; j < N; ++j) ln[j] = sQ[v * N3 + s0 + j * st];
+      for (int j = 0; j < N; ++j) ln[j] = sQ[v * N3 + swz<N>(s0 + j * st)];
       const T j0 = sU[((2 * d) * 9 + v) * N2 + pq], jN = sU[((2 * d + 1) * 9 + v) * N2 + pq];
-      T* out = sG + (v * 3 + d) * N3 + s0;
+      T* out = sG + (v * 3 + d) * N3;
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         T dd = tb.D[i][0] * j0 + tb.D[i][N] * jN;
 #pragma unroll
         for (int j = 0; j < N; ++j) dd += tb.DI[i][j] * ln[j];
-        out[i * st] = dd;
+        out[swz<N>(s0 + i * st)] = dd;
       }
     }
     __syncthreads();
@@ -483,7 +494,7 @@ void k_volume(Launch L) {
     if (tid < N3) {
 #pragma unroll
       for (int v = 0; v < 9; ++v) {
-        T* g = sG + v * 3 * N3 + tid;
+        T* g = sG + v * 3 * N3 + swz<N>(tid);
         const T d0 = g[0], d1 = g[N3], d2 = g[2 * N3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) g[c * N3] = Sj[0][c] * d0 + Sj[1][c] * d1 + Sj[2][c] * d2;
@@ -501,7 +512,8 @@ void k_volume(Launch L) {
         const double rho = q[0];
         const double m2 = q[N3] * q[N3] + q[2 * N3] * q[2 * N3] + q[3 * N3] * q[3 * N3];
         const double b2 = q[5 * N3] * q[5 * N3] + q[6 * N3] * q[6 * N3] + q[7 * N3] * q[7 * N3];
-        const double db = (double)sG[15 * N3 + sp] + (double)sG[19 * N3 + sp] + (double)sG[23 * N3 + sp];
+        const int sx = swz<N>(sp);
+        const double db = (double)sG[15 * N3 + sx] + (double)sG[19 * N3 + sx] + (double)sG[23 * N3 + sx];
         acc[0] = wq;
         acc[1] = wq * rho;
         acc[2] = wq * q[4 * N3];
@@ -592,7 +604,7 @@ void k_volume(Launch L) {
       } else {
         // physical wall
         const T nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        const T inn = T(1) / nn;
+        const T inn = recip(nn);
         const T nh[3] = {n[0] * inn, n[1] * inn, n[2] * inn};
         wall_mirror(qf, nh, g, P, qx);
         rusanov(qf, qx, n, P, F);
@@ -665,15 +677,16 @@ void k_volume(Launch L) {
       const int sp = tid;
       T q[9];
 #pragma unroll
-      for (int v = 0; v < 9; ++v) q[v] = sQ[v * N3 + sp];
+      for (int v = 0; v < 9; ++v) q[v] = sQ[v * N3 + swz<N>(sp)];
       T gv[3] = {T(0), T(0), T(0)};
       if (P.GM != T(0)) {
         const T r2 = xs[0] * xs[0] + xs[1] * xs[1] + xs[2] * xs[2];
         const T sc = -P.GM / (r2 * sqrt(r2));
         gv[0] = sc * xs[0]; gv[1] = sc * xs[1]; gv[2] = sc * xs[2];
       }
-      const T ir = T(1) / q[0];
-      const T db = P.powell ? sG[15 * N3 + sp] + sG[19 * N3 + sp] + sG[23 * N3 + sp] : T(0);
+      const T ir = recip(q[0]);
+      const int sx = swz<N>(sp);
+      const T db = P.powell ? sG[15 * N3 + sx] + sG[19 * N3 + sx] + sG[23 * N3 + sx] : T(0);
       const T uB = (q[1] * q[5] + q[2] * q[6] + q[3] * q[7]) * ir;
       T M[9];
       M[0] = T(0);
@@ -732,7 +745,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
     for (int sp = tid; sp < N3; sp += BS) {
       const int ia[3] = {sp % N, (sp / N) % N, sp / N2};
       // this SP's own-element inputs are requested before the gather below
-      const T ji = T(1) / (T)R.detJ[e * N3 + sp];
+      const T ji = recip((T)R.detJ[e * N3 + sp]);
       const GBL T* rp = R.Rp + e * 9 * N3 + sp;
       T rpv[9];
 #pragma unroll

@@ -1,0 +1,98 @@
+"""GPU edge cases: every supported degree (p = 1 .. 6; p = 6 is the largest
+whose FP64 workgroup fits in LDS), and the error paths of the C ABI that
+guard a launch (every bad argument is rejected on the host before any
+kernel runs)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2502_17805_amd import inputs as inp
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2502_17805_amd import sdmhd
+    return sdmhd
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 6])
+def test_every_degree_residual_and_step(sd, oracle, p):
+    import torch
+    print(f"degree p={p}", flush=True)
+    ml = sd.shell(2, 1, p)
+    mo = oracle.Mesh.shell(p + 1, 2, 1)
+    bg = inp.Background(3.0)
+    Q = inp.shell_state(ml.x_sp, bg, 5)
+    pr = inp.run_params(5, bg)
+    ch = inp.glm_speed(Q)
+    pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
+    pg, po = sd.make_params(**pr), oracle.make_params(**pr)
+    s = sd.Solver(ml)
+    Rg = s.residual(pg, torch.from_numpy(Q).cuda()).cpu().numpy()
+    Ro, ts = mo.residual(po, Q, with_scale=True)
+    assert (np.abs(Rg - Ro).max(axis=(0, 2)) <= TOL * ts).all()
+    dt = inp.time_step(Q, ml.Sj_sp, ch, 0.1)
+    s.set_state(Q)
+    s.step(pg, dt)
+    qo = mo.step(po, Q, dt)
+    err = np.abs(s.state.cpu().numpy() - qo).max(axis=(0, 2))
+    assert (err <= TOL * (np.abs(qo).max(axis=(0, 2)) + dt * ts)).all()
+
+
+def _ctx(sd, p=3, arith=0):
+    h = C.c_void_p()
+    assert sd._lib.sdm_create(0, p, arith, C.byref(h)) == sd.SDM_OK
+    return h
+
+
+def test_create_rejects_unsupported_degree(sd):
+    h = C.c_void_p()
+    for p, arith in ((0, 0), (7, 0), (3, 2)):
+        assert sd._lib.sdm_create(0, p, arith, C.byref(h)) != sd.SDM_OK
+        assert sd._lib.sdm_last_error()
+
+
+def test_mesh_bind_rejects_empty_and_corrupt_tables(sd):
+    import torch
+    m = sd.shell(1, 1, 3)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(getattr(m, k))).cuda()
+           for k in ("x_sp", "detJ", "S_fp", "Sj_sp", "nbr", "n_face")}
+    h = _ctx(sd)
+    try:
+        def desc(E, NB, nbr):
+            return sd.MeshDesc(E, NB, dev["x_sp"].data_ptr(), dev["detJ"].data_ptr(), dev["S_fp"].data_ptr(),
+                               dev["Sj_sp"].data_ptr(), nbr.data_ptr(), dev["n_face"].data_ptr())
+        assert sd._lib.sdm_mesh_bind(h, C.byref(desc(0, 0, dev["nbr"]))) != sd.SDM_OK
+        for bad in (m.E << 6, -(1 + 3 + 4 * 0), -(1 + 4 * m.NB)):  # element, wall group, boundary face
+            nb = dev["nbr"].clone()
+            nb[0, 0] = int(bad)
+            assert sd._lib.sdm_mesh_bind(h, C.byref(desc(m.E, m.NB, nb))) != sd.SDM_OK, bad
+        assert sd._lib.sdm_mesh_bind(h, C.byref(desc(m.E, m.NB, dev["nbr"]))) == sd.SDM_OK
+        nb = C.c_size_t()
+        assert sd._lib.sdm_workspace_size(h, C.byref(nb)) == sd.SDM_OK and nb.value > 0
+    finally:
+        sd._lib.sdm_destroy(h)
+
+
+def test_dirichlet_mesh_requires_ghost(sd):
+    import torch
+    m = sd.box(3, 3, 2, 3, periodic=3)  # the z faces are boundary faces
+    s = sd.Solver(m)
+    Q = torch.from_numpy(inp.smooth_random_state(m.x_sp, 1)).cuda()
+    s.residual(sd.make_params(c_h=1.0), Q)  # as walls: no ghost state needed
+    with pytest.raises(sd.SdmError):  # as Dirichlet faces: the ghost state is required
+        s.residual(sd.make_params(c_h=1.0, wall_kind=(1, 1)), Q)
+
+
+def test_batch_rejects_empty_and_mismatched(sd):
+    nb = C.c_size_t()
+    assert sd._lib.sdm_batch_workspace_size(0, C.byref(nb)) != sd.SDM_OK
+    items = (sd.BatchItem * 1)()
+    assert sd._lib.sdm_batch_stage(items, 0, None, 0, 0, None) != sd.SDM_OK
