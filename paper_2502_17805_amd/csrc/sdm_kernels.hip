@@ -369,6 +369,9 @@ void k_volume(Launch L) {
   __shared__ T sU[UN];  // face jumps (common value - own trace), then fluxes
   __shared__ double sRed[BS / 64][10];
   __shared__ T sI[(N + 1) * N], sD[N * (N + 1)];
+  // the physical parameters, read from LDS where they are used: held in
+  // scalar registers for the whole element they overflow them
+  __shared__ Phys<T> sP;
   static_assert(BS >= N3, "one solution point per thread");
   const DevTab<T>& tb = tab<T>(N);
   const int tid = threadIdx.x;
@@ -381,11 +384,12 @@ void k_volume(Launch L) {
     if (w >= L.n_work) return;
     const Run<T> R = view<T>(L, w);
     const int64_t e = R.e;
-    const Phys<T>& P = R.P;
+    if (tid == 0) sP = R.P;
+    const Phys<T>& P = sP;  // valid after the barrier that ends phase A
     const GBL double* Qe = R.Q + e * 9 * N3;
     const GBL double* Se = R.S_fp + e * 9 * NF;
     const GBL int32_t* nb6 = R.nbr + e * 6;
-    const bool use_kr = P.kr_scale != T(0);
+    const bool use_kr = R.P.kr_scale != T(0);
 
     // A. every global read of this element is issued here: the state into
     //    LDS; the chain-rule factors and position of this thread's SP; the
@@ -480,7 +484,9 @@ void k_volume(Launch L) {
       for (int j = 0; j < N; ++j) ln[j] = sQ[v * N3 + swz<N>(s0 + j * st)];
       const T j0 = sU[((2 * d) * 9 + v) * N2 + pq], jN = sU[((2 * d + 1) * 9 + v) * N2 + pq];
       T* out = sG + (v * 3 + d) * N3;
-#pragma unroll
+      // one row of the tables per step (scalar loads), not all N^2 + 2N
+      // entries held in scalar registers at once
+#pragma unroll 1
       for (int i = 0; i < N; ++i) {
         T dd = tb.D[i][0] * j0 + tb.D[i][N] * jN;
 #pragma unroll
