@@ -718,11 +718,11 @@ void k_volume(Launch L) {
 template <int N, typename T, bool STAGE>
 __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
   constexpr int N2 = N * N, N3 = N2 * N, NP = N + 1, BS = block_threads<N>();
+  static_assert(BS >= N3, "one solution point per thread");
   __shared__ T sV[6 * 7 * N2];
   __shared__ double sOut[STAGE ? 9 * N3 : 1];
   __shared__ T sI[(N + 1) * N], sD[N * (N + 1)];
   const int tid = threadIdx.x;
-  stage_tables<N>(sI, sD);
   {
     // one element per workgroup; no loop, so nothing per element is kept
     // live across elements
@@ -731,6 +731,32 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
     const Run<T> R = view<T>(L, w);
     const int64_t e = R.e;
     const GBL int32_t* nb6 = R.nbr + e * 6;
+    // this thread's SP: its own-element inputs are requested first (they do
+    // not depend on the gather): 1/|J|, the partial residual and, for a
+    // stage, the Shu-Osher combination sum_k alpha_k u_k of the registers
+    const int sp = tid;
+    T ji = T(0), rpv[9];
+    double u[9];
+    if (sp < N3) {
+      ji = recip((T)R.detJ[e * N3 + sp]);
+      const GBL T* rp = R.Rp + e * 9 * N3 + sp;
+#pragma unroll
+      for (int v = 0; v < 9; ++v) rpv[v] = rp[v * N3];
+      if (STAGE) {
+#pragma unroll
+        for (int v = 0; v < 9; ++v) u[v] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (k < R.n_in) {
+            const double a = R.alpha[k];
+            const GBL double* src = R.in[k] + e * 9 * N3 + sp;
+#pragma unroll
+            for (int v = 0; v < 9; ++v) u[v] += a * src[v * N3];
+          }
+        }
+      }
+    }
+    // the neighbours' viscous normal fluxes on the six faces
     for (int it = tid; it < 6 * N2; it += BS) {
       const int f = it / N2, ab = it % N2;
       const int32_t code = nb6[f];
@@ -747,31 +773,10 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
         for (int c = 0; c < 7; ++c) sV[(f * 7 + c) * N2 + ab] = T(0);
       }
     }
+    stage_tables<N>(sI, sD);
     __syncthreads();
-    for (int sp = tid; sp < N3; sp += BS) {
+    if (sp < N3) {
       const int ia[3] = {sp % N, (sp / N) % N, sp / N2};
-      // this SP's own-element inputs are requested before the gather below
-      const T ji = recip((T)R.detJ[e * N3 + sp]);
-      const GBL T* rp = R.Rp + e * 9 * N3 + sp;
-      T rpv[9];
-#pragma unroll
-      for (int v = 0; v < 9; ++v) rpv[v] = rp[v * N3];
-      double u[9];
-      if (STAGE) {
-        // Shu-Osher stage in FP64: sum_k alpha_k u_k + beta dt R; the
-        // register reads do not depend on each other
-#pragma unroll
-        for (int v = 0; v < 9; ++v) u[v] = 0.0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (k < R.n_in) {
-            const double a = R.alpha[k];
-            const GBL double* src = R.in[k] + e * 9 * N3 + sp;
-#pragma unroll
-            for (int v = 0; v < 9; ++v) u[v] += a * src[v * N3];
-          }
-        }
-      }
       T corr[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -793,28 +798,30 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
 #pragma unroll
         for (int v = 0; v < 9; ++v) Ro[v * N3] = Rv[v];
       } else {
+        // Shu-Osher stage in FP64: sum_k alpha_k u_k + beta dt R
+        GBL double* out = R.out + e * 9 * N3 + sp;
 #pragma unroll
-        for (int v = 0; v < 9; ++v) sOut[v * N3 + sp] = u[v] + R.beta_dt * Rv[v];
-      }
-    }
-    if (STAGE) {
-      __syncthreads();
-      GBL double* out = R.out + e * 9 * N3;
-      for (int i = tid; i < 9 * N3; i += BS) out[i] = sOut[i];
-      if (R.write_traces) {
-        GBL T* tr = R.Qtr + e * 6 * 9 * N2;
-        for (int it = tid; it < 6 * 9 * N2; it += BS) {
-          const int ab = it % N2, fv = it / N2, v = fv % 9, f = fv / 9;
-          const int d = f >> 1;
-          const T* wI = sI + ((f & 1) ? N : 0) * N;
-          T s = T(0);
-#pragma unroll
-          for (int i = 0; i < N; ++i) s += wI[i] * (T)sOut[v * N3 + sp_line<N>(d, ab % N, ab / N, i)];
-          tr[it] = s;
+        for (int v = 0; v < 9; ++v) {
+          const double x = u[v] + R.beta_dt * Rv[v];
+          out[v * N3] = x;
+          sOut[v * N3 + sp] = x;
         }
       }
     }
-    __syncthreads();
+    if (STAGE && R.write_traces) {
+      // the new state's face traces for the next stage
+      __syncthreads();
+      GBL T* tr = R.Qtr + e * 6 * 9 * N2;
+      for (int it = tid; it < 6 * 9 * N2; it += BS) {
+        const int ab = it % N2, fv = it / N2, v = fv % 9, f = fv / 9;
+        const int d = f >> 1;
+        const T* wI = sI + ((f & 1) ? N : 0) * N;
+        T s = T(0);
+#pragma unroll
+        for (int i = 0; i < N; ++i) s += wI[i] * (T)sOut[v * N3 + sp_line<N>(d, ab % N, ab / N, i)];
+        tr[it] = s;
+      }
+    }
   }
 }
 
