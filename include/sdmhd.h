@@ -31,7 +31,10 @@
  *                       neighbour element e', its face f', orientation o.
  *                       Boundary: -(1 + group + 4 * bface), group 0 = zeta=0
  *                       wall (inner sphere), 1 = zeta=1 wall (outer sphere),
- *                       2 = other (always Dirichlet); bface numbers the
+ *                       2 = other (always Dirichlet), 3 = import face (the
+ *                       neighbour belongs to another partition of the
+ *                       mesh: its trace and viscous flux come from the
+ *                       import buffers of sdm_params); bface numbers the
  *                       boundary faces in (element, face) order.
  *   face-local point (a, b): the two axes other than the face normal, in
  *   increasing axis order; orientation o = 4 swap + 2 flip_b + flip_a maps
@@ -42,6 +45,13 @@
  *                       outward metric vectors (exact negatives across the
  *                       face); S_own on boundary faces (FP64)
  *   ghost  [n_bfaces][9][N^2]  outside state on Dirichlet faces (device).
+ *   import_q [n_bfaces][9][N^2], import_v [n_bfaces][7][N^2]  on import faces:
+ *                       the neighbour's Q trace and its viscous normal flux
+ *                       (components 1..7 of the BR1 viscous flux through the
+ *                       symmetric normal, as the neighbour's own workspace
+ *                       holds them), already in this face's point order, in
+ *                       the residual arithmetic type (FP64, or FP32 for a
+ *                       mixed context); rows of other faces are not read.
  *
  * Errors: every call returns an sdm_status; nothing is thrown across the
  * ABI.  SDM_EINVAL: bad sizes, NULL pointers, unsupported p; SDM_EHIP: a HIP
@@ -154,12 +164,24 @@ typedef struct {
   int32_t wall_th[2];
   double q_wall[2];
   double T_wall[2];
-  const double* ghost; /* device [n_bfaces][9][N^2] or NULL */
+  const double* ghost;    /* device [n_bfaces][9][N^2] or NULL */
+  const void* import_q;   /* device [n_bfaces][9][N^2] or NULL (needed with import faces) */
+  const void* import_v;   /* device [n_bfaces][7][N^2] or NULL (needed with import faces) */
 } sdm_params;
 
 /* Bytes of scratch (face traces, partial residual) one call needs; the
  * caller allocates it (device, 256-byte aligned) and passes it as `ws`. */
 sdm_status sdm_workspace_size(const sdm_ctx* ctx, size_t* bytes);
+
+/* Device addresses, inside workspace `ws`, of the face traces a partition
+ * sends to its neighbours (the halo of a mesh split over several GPUs; the
+ * receiving side passes them, orientation-mapped to its face points, as
+ * import_q / import_v): q_traces [E][6][9][N^2] = Q at the six faces of
+ * every element, of the state the next stage takes (written by each stage
+ * and by sdm_residual for its Q); v_traces [E][6][7][N^2] = the element's
+ * own viscous normal flux at its faces from the last residual evaluation.
+ * Residual arithmetic type.  Views only: nothing is copied. */
+sdm_status sdm_workspace_traces(const sdm_ctx* ctx, void* ws, void** q_traces, void** v_traces);
 
 /* R = dQ/dt at the solution points (device Q, R, layout [E][9][N3]). */
 sdm_status sdm_residual(sdm_ctx* ctx, const sdm_params* prm, const double* Q, double* R,

@@ -71,6 +71,8 @@ struct RunDesc {
   const int32_t* nbr;
   const double* n_face;
   const double* ghost;
+  const void* imp_q;   // [n_bfaces][9][N2]  T  neighbour traces on import faces
+  const void* imp_v;   // [n_bfaces][7][N2]  T  neighbour viscous normal fluxes
   const double* Q;     // state whose residual is taken
   void* Qtr;           // [E][6][9][N2]  T
   void* Vtr;           // [E][6][7][N2]  T
@@ -109,6 +111,8 @@ struct Run {
   const GBL int32_t* nbr;
   const GBL double* n_face;
   const GBL double* ghost;
+  const GBL T* imp_q;
+  const GBL T* imp_v;
   const GBL double* Q;
   GBL T* Qtr;
   GBL T* Vtr;
@@ -149,6 +153,8 @@ __device__ __forceinline__ void fill_run(Run<T>& r, S& d) {
   r.nbr = (const GBL int32_t*)d.nbr;
   r.n_face = (const GBL double*)d.n_face;
   r.ghost = (const GBL double*)d.ghost;
+  r.imp_q = (const GBL T*)d.imp_q;
+  r.imp_v = (const GBL T*)d.imp_v;
   r.Q = (const GBL double*)d.Q;
   r.Qtr = (GBL T*)d.Qtr;
   r.Vtr = (GBL T*)d.Vtr;
@@ -282,7 +288,11 @@ __device__ __forceinline__ void load_outside(const Run<T>& R, int f, int ab, int
   } else {
     const int c2 = -code - 1, g = c2 & 3;
     const int64_t bf = c2 >> 2;
-    if (g == 2 || wsel(g, R.P.wall_kind) == 1) {
+    if (g == 3) {
+      const GBL T* tn = R.imp_q + bf * 9 * N2 + ab;
+#pragma unroll
+      for (int v = 0; v < 9; ++v) q[v] = tn[v * N2];
+    } else if (g == 2 || wsel(g, R.P.wall_kind) == 1) {
       const GBL double* gh = R.ghost + bf * 9 * N2 + ab;
 #pragma unroll
       for (int v = 0; v < 9; ++v) q[v] = (T)gh[v * N2];
@@ -454,7 +464,7 @@ void k_volume(Launch L) {
       const T* own = sTr + f * 9 * N2 + ab;
       T* dst = sU + f * 9 * N2 + ab;
       const int g = code >= 0 ? -1 : ((-code - 1) & 3);
-      if (code >= 0 || g == 2 || wsel(g, P.wall_kind) == 1) {
+      if (code >= 0 || g >= 2 || wsel(g, P.wall_kind) == 1) {
 #pragma unroll
         for (int v = 0; v < 9; ++v) dst[v * N2] = T(0.5) * (q_out[v] - own[v * N2]);
       } else {
@@ -583,8 +593,9 @@ void k_volume(Launch L) {
       T F[9];
       ViscLocal<T> vl;
       const int g = code >= 0 ? -1 : ((-code - 1) & 3);
-      if (code >= 0) {
-        // interior face: Rusanov on the symmetric normal, own half of BR1 viscous
+      if (code >= 0 || g == 3) {
+        // interior (or import) face: Rusanov on the symmetric normal, own half
+        // of the BR1 viscous flux
         viscous_local(qf, gf, kf, P, vl);
         T Fv[7];
         flux_viscous7(vl, n, P, Fv);
@@ -768,6 +779,10 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
         const GBL T* src = R.Vtr + (en * 6 + fn) * 7 * N2 + a2 + N * b2;
 #pragma unroll
         for (int c = 0; c < 7; ++c) sV[(f * 7 + c) * N2 + ab] = src[c * N2];
+      } else if (((-code - 1) & 3) == 3) {  // import face: the neighbour's flux as given
+        const GBL T* src = R.imp_v + (int64_t)((-code - 1) >> 2) * 7 * N2 + ab;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) sV[(f * 7 + c) * N2 + ab] = src[c * N2];
       } else {
 #pragma unroll
         for (int c = 0; c < 7; ++c) sV[(f * 7 + c) * N2 + ab] = T(0);
@@ -944,7 +959,7 @@ struct sdm_ctx {
   int arith = 0;
   bool bound = false;
   sdm_mesh mesh{};
-  int64_t n_group[3] = {0, 0, 0};  // boundary faces per group
+  int64_t n_group[4] = {0, 0, 0, 0};  // boundary faces per group
   // optional per-kernel timing: events recorded around every launch
   bool prof = false;
   std::vector<hipEvent_t> ev;
@@ -983,6 +998,8 @@ sdm_status check_params(const sdm_ctx* c, const sdm_params* p) {
   const bool need_ghost = c->n_group[2] > 0 || (c->n_group[0] > 0 && p->wall_kind[0] == 1) ||
                           (c->n_group[1] > 0 && p->wall_kind[1] == 1);
   if (need_ghost && !p->ghost) return fail(SDM_EINVAL, "Dirichlet faces present but ghost is NULL");
+  if (c->n_group[3] > 0 && (!p->import_q || !p->import_v))
+    return fail(SDM_EINVAL, "import faces present but import_q or import_v is NULL");
   return SDM_OK;
 }
 
@@ -1000,6 +1017,8 @@ RunDesc make_desc(const sdm_ctx* c, const sdm_params* p, const double* Q, void* 
   r.nbr = c->mesh.nbr;
   r.n_face = c->mesh.n_face;
   r.ghost = p ? p->ghost : nullptr;
+  r.imp_q = p ? p->import_q : nullptr;
+  r.imp_v = p ? p->import_v : nullptr;
   r.Q = Q;
   r.Qtr = (char*)ws + off[0];
   r.Vtr = (char*)ws + off[1];
@@ -1257,7 +1276,7 @@ sdm_status sdm_mesh_bind(sdm_ctx* c, const sdm_mesh* m) {
   std::vector<int32_t> nb((size_t)m->n_elem * 6);
   HIP_TRY(hipSetDevice(c->device));
   HIP_TRY(hipMemcpy(nb.data(), m->nbr, sizeof(int32_t) * nb.size(), hipMemcpyDeviceToHost));
-  int64_t ng[3] = {0, 0, 0};
+  int64_t ng[4] = {0, 0, 0, 0};
   for (int64_t i = 0; i < (int64_t)nb.size(); ++i) {
     const int32_t code = nb[i];
     if (code >= 0) {
@@ -1268,12 +1287,12 @@ sdm_status sdm_mesh_bind(sdm_ctx* c, const sdm_mesh* m) {
       const int64_t c2 = -(int64_t)code - 1;
       const int g = (int)(c2 & 3);
       const int64_t bf = c2 >> 2;
-      if (g > 2 || bf >= m->n_bfaces) return fail(SDM_EINVAL, "mesh_bind: boundary code out of range");
+      if (bf >= m->n_bfaces) return fail(SDM_EINVAL, "mesh_bind: boundary code out of range");
       ++ng[g];
     }
   }
   c->mesh = *m;
-  for (int g = 0; g < 3; ++g) c->n_group[g] = ng[g];
+  for (int g = 0; g < 4; ++g) c->n_group[g] = ng[g];
   c->bound = true;
   return SDM_OK;
 }
@@ -1284,6 +1303,16 @@ sdm_status sdm_workspace_size(const sdm_ctx* c, size_t* bytes) {
   size_t off[4];
   ws_layout(c, off);
   *bytes = off[3];
+  return SDM_OK;
+}
+
+sdm_status sdm_workspace_traces(const sdm_ctx* c, void* ws, void** q_traces, void** v_traces) {
+  if (!c || !ws || !q_traces || !v_traces) return fail(SDM_EINVAL, "workspace_traces: NULL argument");
+  if (!c->bound) return fail(SDM_ESTATE, "workspace_traces: no mesh bound");
+  size_t off[4];
+  ws_layout(c, off);
+  *q_traces = (char*)ws + off[0];
+  *v_traces = (char*)ws + off[1];
   return SDM_OK;
 }
 

@@ -45,7 +45,7 @@ class Params(C.Structure):
                                           "c_h", "glm_a")] + [
         ("powell", C.c_int32), ("wall_kind", C.c_int32 * 2), ("wall_mag", C.c_int32 * 2),
         ("wall_th", C.c_int32 * 2), ("q_wall", C.c_double * 2), ("T_wall", C.c_double * 2),
-        ("ghost", C.c_void_p)]
+        ("ghost", C.c_void_p), ("import_q", C.c_void_p), ("import_v", C.c_void_p)]
 
 
 class Stage(C.Structure):
@@ -81,6 +81,7 @@ _lib.sdm_create.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]
 _lib.sdm_destroy.argtypes = [_vp]
 _lib.sdm_mesh_bind.argtypes = [_vp, C.POINTER(MeshDesc)]
 _lib.sdm_workspace_size.argtypes = [_vp, C.POINTER(C.c_size_t)]
+_lib.sdm_workspace_traces.argtypes = [_vp, _vp, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]
 _lib.sdm_residual.argtypes = [_vp, C.POINTER(Params), _vp, _vp, _vp, _vp]
 _lib.sdm_rk_stage.argtypes = [_vp, C.POINTER(Params), C.POINTER(C.c_void_p), C.c_int,
                               C.POINTER(Stage), C.c_double, _vp, _vp]
@@ -92,13 +93,14 @@ _lib.sdm_profile_read.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int6
 for _f in ("sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes", "sdm_box_build", "sdm_tables",
            "sdm_create", "sdm_destroy", "sdm_mesh_bind", "sdm_workspace_size", "sdm_residual",
            "sdm_rk_stage", "sdm_diagnostics", "sdm_profile_enable", "sdm_profile_read",
-           "sdm_batch_workspace_size", "sdm_batch_stage"):
+           "sdm_batch_workspace_size", "sdm_batch_stage", "sdm_workspace_traces"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTED = ("sdm_last_error", "sdm_version", "sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes",
             "sdm_box_build", "sdm_tables", "sdm_create", "sdm_destroy", "sdm_mesh_bind",
             "sdm_workspace_size", "sdm_residual", "sdm_rk_stage", "sdm_diagnostics",
-            "sdm_profile_enable", "sdm_profile_read", "sdm_batch_workspace_size", "sdm_batch_stage")
+            "sdm_profile_enable", "sdm_profile_read", "sdm_batch_workspace_size", "sdm_batch_stage",
+            "sdm_workspace_traces")
 KERNELS = ("traces", "volume", "volume_diag", "finish_residual", "finish_stage")
 
 
@@ -115,7 +117,9 @@ def _p(a):
     return C.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else C.c_void_p(a.data_ptr())
 
 
-def make_params(ghost=None, **kw) -> Params:
+def make_params(ghost=None, import_q=None, import_v=None, **kw) -> Params:
+    """sdm_params from keyword values; ghost / import_q / import_v are device
+    tensors (or None) that must outlive the calls using the parameters."""
     p = Params()
     d = dict(gamma=5.0 / 3.0, Rgas=1.0, GM=0.0, Omega=0.0, nu=0.0, kappa=0.0, eta=0.0,
              kr_scale=0.0, kr_c0=0.0, kr_c1=0.0, kr_c2=0.0, kr_omega_per_r=0.0, c_h=0.0, glm_a=0.0,
@@ -134,6 +138,8 @@ def make_params(ghost=None, **kw) -> Params:
         else:
             setattr(p, k, float(v))
     p.ghost = None if ghost is None else ghost.data_ptr()
+    p.import_q = None if import_q is None else import_q.data_ptr()
+    p.import_v = None if import_v is None else import_v.data_ptr()
     return p
 
 
@@ -178,6 +184,85 @@ def box(nx, ny, nz, p, L=(1.0, 1.0, 1.0), periodic=7, warp=0.0) -> Mesh:
     _check(_lib.sdm_box_build(nx, ny, nz, L[0], L[1], L[2], periodic, warp, p, _p(m.x_sp), _p(m.detJ),
                               _p(m.S_fp), _p(m.Sj_sp), _p(m.nbr), _p(m.n_face)))
     return m
+
+
+def face_point_map(N: int) -> np.ndarray:
+    """[8][N^2]: for orientation code o, the neighbour's face-point index
+    a' + N b' of this side's face point a + N b (the map of include/sdmhd.h)."""
+    out = np.zeros((8, N * N), dtype=np.int64)
+    for o in range(8):
+        for b in range(N):
+            for a in range(N):
+                p, q = (b, a) if o & 4 else (a, b)
+                a2 = N - 1 - p if o & 1 else p
+                b2 = N - 1 - q if o & 2 else q
+                out[o, a + N * b] = a2 + N * b2
+    return out
+
+
+@dataclasses.dataclass
+class Shard:
+    """One partition of a mesh, as one GPU of a split run holds it.
+
+    mesh     the partition's own arrays; faces whose neighbour lies in another
+             partition are boundary faces of group 3 (import faces)
+    elems    [E_local] global index of each local element
+    bface    [NB_local] global boundary-face index of each local boundary
+             face, -1 for import faces (re-indexes ghost rows)
+    imports  [n_imp][4] local boundary-face index, neighbour's global element,
+             its face, orientation code: where each import face's data comes from
+    """
+    mesh: Mesh
+    elems: np.ndarray
+    bface: np.ndarray
+    imports: np.ndarray
+
+
+def make_shard(mesh: Mesh, elems) -> Shard:
+    """The partition of `mesh` made of the (global) elements `elems`.  The
+    metrics and face normals are the full mesh's rows, so the symmetric face
+    normals of partition faces are those of the unsplit mesh."""
+    elems = np.asarray(elems, dtype=np.int64)
+    E = len(elems)
+    loc = -np.ones(mesh.E, dtype=np.int64)
+    loc[elems] = np.arange(E)
+    nbr = np.zeros((E, 6), dtype=np.int32)
+    bface, imports = [], []
+    for le, ge in enumerate(elems):
+        for f in range(6):
+            code = int(mesh.nbr[ge, f])
+            if code >= 0 and loc[code >> 6] >= 0:
+                nbr[le, f] = (int(loc[code >> 6]) << 6) | (code & 63)
+                continue
+            bf = len(bface)
+            if code >= 0:  # neighbour in another partition: import face
+                group, gbf = 3, -1
+                imports.append((bf, code >> 6, (code >> 3) & 7, code & 7))
+            else:
+                group, gbf = (-code - 1) & 3, (-code - 1) >> 2
+            nbr[le, f] = -(1 + group + 4 * bf)
+            bface.append(gbf)
+    m = Mesh(mesh.p, E, len(bface), mesh.x_sp[elems].copy(), mesh.detJ[elems].copy(), mesh.S_fp[elems].copy(),
+             mesh.Sj_sp[elems].copy(), nbr, mesh.n_face[elems].copy())
+    return Shard(m, elems, np.asarray(bface, dtype=np.int64), np.asarray(imports, dtype=np.int64).reshape(-1, 4))
+
+
+def gather_imports(shard: Shard, q_traces, v_traces):
+    """Import buffers of a partition from the neighbours' workspace traces
+    (torch tensors [E_global][6][9][N^2] and [E_global][6][7][N^2], e.g. the
+    views of a run over the whole mesh): each import face gets its
+    neighbour's trace and viscous flux in this face's point order."""
+    import torch
+    N2 = q_traces.shape[-1]
+    pm = torch.as_tensor(face_point_map(shard.mesh.N), device=q_traces.device)
+    imp = torch.as_tensor(shard.imports, device=q_traces.device)
+    out_q = torch.zeros((shard.mesh.NB, 9, N2), dtype=q_traces.dtype, device=q_traces.device)
+    out_v = torch.zeros((shard.mesh.NB, 7, N2), dtype=v_traces.dtype, device=v_traces.device)
+    if len(imp):
+        e, f, pts = imp[:, 1, None, None], imp[:, 2, None, None], pm[imp[:, 3]][:, None, :]
+        out_q[imp[:, 0]] = q_traces[e, f, torch.arange(9, device=pm.device)[None, :, None], pts]
+        out_v[imp[:, 0]] = v_traces[e, f, torch.arange(7, device=pm.device)[None, :, None], pts]
+    return out_q, out_v
 
 
 def tables(p: int):
@@ -258,6 +343,22 @@ class Solver:
                 self._h = None
         except Exception:
             pass
+
+    def trace_views(self):
+        """(q_traces [E][6][9][N^2], v_traces [E][6][7][N^2]) as tensors viewing
+        the workspace (residual arithmetic type): what this partition sends to
+        its neighbours (sdm_workspace_traces)."""
+        q, v = C.c_void_p(), C.c_void_p()
+        _check(_lib.sdm_workspace_traces(self._h, self.ws.data_ptr(), C.byref(q), C.byref(v)))
+        dt = self.torch.float64 if self.arith == 0 else self.torch.float32
+        isz = 8 if self.arith == 0 else 4
+        E, N2 = self.mesh.E, self.mesh.N ** 2
+        base = self.ws.data_ptr()
+
+        def view(ptr, nvar):
+            off = ptr - base
+            return self.ws[off:off + E * 6 * nvar * N2 * isz].view(dt).view(E, 6, nvar, N2)
+        return view(q.value, 9), view(v.value, 7)
 
     def _stream(self):
         return C.c_void_p(self.torch.cuda.current_stream(self.dev).cuda_stream)

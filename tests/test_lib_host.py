@@ -108,3 +108,27 @@ def test_face_normals_symmetric(sd):
                         assert np.abs(n - sown).max() < 1e-12 * np.abs(sown).max()
                     else:
                         assert np.array_equal(n, sown)
+
+
+def test_patch_shard_import_faces(sd):
+    """Cube patch 0 of a shell as a partition: 4 Nz Nr import faces, every
+    one pointing at an element outside the partition; the two sides of each
+    partition face carry exactly negated normals at corresponding points
+    (the orientation map of the import gather is right)."""
+    m = sd.shell(3, 2, 3)
+    sh = sd.make_shard(m, np.arange(m.E // 6))
+    assert sh.mesh.E == 18 and len(sh.imports) == 4 * 3 * 2
+    assert sh.mesh.NB == len(sh.imports) + 2 * 9 and (sh.bface == -1).sum() == len(sh.imports)
+    pm = sd.face_point_map(m.N)
+    inside = set(range(m.E // 6))
+    for bf, ge, f2, o in sh.imports:
+        assert ge not in inside
+        le, f = np.argwhere(sh.mesh.nbr == -(1 + 3 + 4 * bf))[0]
+        assert np.array_equal(sh.mesh.n_face[le, f], -m.n_face[ge, f2][:, pm[o]])
+    # every interior code of the partition points inside it, faces match back
+    for le in range(sh.mesh.E):
+        for f in range(6):
+            c = int(sh.mesh.nbr[le, f])
+            if c >= 0:
+                e2, f2 = c >> 6, (c >> 3) & 7
+                assert (int(sh.mesh.nbr[e2, f2]) >> 6) == le
