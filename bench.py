@@ -123,6 +123,38 @@ def run_gpu(sd, inp, cfg_name, arith, steps, warmup, mesh, Q, pr, dt):
     return ms, wall, prof, d
 
 
+def run_shard(sd, mesh, Q, pr, dt, steps, warmup):
+    """One GPU's share of the shell split by cube patch (6 ways): patch 0 with
+    its partition faces as import faces.  The halo buffers are filled once
+    from an unsplit residual evaluation (a split run would refresh them
+    between the launches of every stage); the timed work is the partition's
+    own stages."""
+    import torch
+    sh = sd.make_shard(mesh, np.arange(mesh.E // 6))
+    sf = sd.Solver(mesh)
+    sf.residual(sd.make_params(**pr), torch.from_numpy(Q).cuda())
+    iq, iv = sd.gather_imports(sh, *sf.trace_views())
+    del sf
+    s = sd.Solver(sh.mesh)
+    prm = sd.make_params(import_q=iq, import_v=iv, **pr)
+    s.set_state(torch.from_numpy(Q[sh.elems]))
+    for _ in range(warmup):
+        s.step(prm, dt)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        s.step(prm, dt)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    dof = sh.mesh.E * sh.mesh.N ** 3
+    return {"workload": f"cube patch 0 of the same shell ({sh.mesh.E} elements, {len(sh.imports)} import faces), "
+                        "FP64, halo buffers fixed", "elements": sh.mesh.E, "ms_per_step": ms,
+            "value": dof * 5 / (ms * 1e-3), "unit": "DOF*RK-stage updates/s"}
+
+
 def cpu_baseline(cfg, Q_fn, pr, dt):
     from oracle import oracle as o
     Nz, Nr, p, _, _ = cfg
@@ -146,6 +178,7 @@ def main():
     ap.add_argument("--config", default="shell_55296_p5", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-shard", action="store_true")
     ap.add_argument("--cfl", type=float, default=0.1)
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="BYTES",
                     help="first run a plain device copy of BYTES bytes (read BYTES, write BYTES) three "
@@ -251,6 +284,9 @@ def main():
         out["mixed_fp32"] = {"value": dof * stages / (ms1 * 1e-3), "ms_per_step": ms1 / args.steps,
                              "kernels_ms_per_step": {k: v[0] / args.steps for k, v in prof1.items()},
                              "speedup_vs_fp64": ms / ms1}
+    if not args.no_shard and args.config != "shell_48_p5":
+        out["shard_6way"] = run_shard(sd, mesh, Q, pr, dt, args.steps, args.warmup)
+        print(f"# shard: {out['shard_6way']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(cfg, lambda x: inp.shell_state(x, bg, seed), pr, dt)
