@@ -11,6 +11,33 @@
  * Only the test suite, the smoke check and the CPU-baseline leg of the
  * benchmark may load this library.  It shares no source with the HIP
  * library; the two meet only through the documented array layouts.
+ *
+ * What pins each part against the paper and the mathematics, not against
+ * itself (tests/test_oracle_*.py):
+ *   or_tables           closed-form points, textbook Legendre roots,
+ *                       exactness of I, D, W on monomials, symmetry
+ *   mesh builders       volume -> closed form, Jacobian positive, discrete
+ *                       GCL, metric = cofactors of the Jacobian, watertight
+ *                       faces with negated normals, boundary nodes on spheres
+ *   point fluxes        Euler limit, GLM/magnetic terms, rotational
+ *                       invariance, viscous closed forms, fast-speed limits,
+ *                       Rusanov consistency and exact antisymmetry
+ *   or_residual         free stream on the curved shell, polynomial
+ *                       exactness on an affine box, mass and energy
+ *                       conservation, heat input = q x wall area, Alfven
+ *                       wave convergence at order p, viscous and resistive
+ *                       decay rates, GLM divergence wave, spherical
+ *                       symmetry, rotation equivariance, hydrostatic
+ *                       convergence
+ *   or_ssprk53_*        order conditions, SSP coefficient, third-order
+ *                       convergence, table = independent derivation
+ *   or_diagnostics      exact integrals of uniform and polynomial states,
+ *                       div B of a linear field, NaN flag
+ * Parity unpinned beyond invariants: the wall treatments (mirror and common
+ * states, stress-free and magnetic wall fluxes) are pinned only by zero
+ * mass flux, zero tangential stress, zero energy flux through a conducting
+ * adiabatic wall and the prescribed heat input; their remaining details
+ * follow the stated readings of the boundary conditions.
  */
 #ifndef SDMHD_ORACLE_H
 #define SDMHD_ORACLE_H
