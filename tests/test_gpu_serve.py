@@ -4,6 +4,8 @@ HBM budget, and through the single-run stage API."""
 import numpy as np
 import pytest
 
+from paper_2502_17805_amd import inputs as inp
+
 pytestmark = pytest.mark.gpu
 
 
@@ -65,3 +67,74 @@ def test_batched_equals_single_run_api(srv):
     for _ in range(3):
         s.step(prm, dt)
     assert np.array_equal(s.state.cpu().numpy(), res[0].state)
+
+
+def _batch_step(sd, solvers, prms, dt, bws, nbytes, stream):
+    """One SSPRK(5,3) step of several solvers through sdm_batch_stage."""
+    import ctypes as C
+    ptrs = [(C.c_void_p * 4)(*[r.data_ptr() for r in s.regs]) for s in solvers]
+    for cur, inputs, beta, out in sd.ssp53_stages():
+        items = (sd.BatchItem * len(solvers))()
+        for k, s in enumerate(solvers):
+            st = sd.Stage()
+            st.n_in = len(inputs)
+            for j, (idx, al) in enumerate(inputs):
+                st.in_idx[j], st.alpha[j] = idx, al
+            st.cur, st.out, st.beta, st.traces_valid = cur, out, beta, 0
+            items[k] = sd.BatchItem(s._h.value, C.pointer(prms[k]), ptrs[k], 4, st, dt, s.ws.data_ptr())
+        sd._check(sd._lib.sdm_batch_stage(items, len(solvers), bws.data_ptr(), nbytes, 0, stream))
+
+
+def test_nan_run_does_not_touch_its_batch_neighbours(srv):
+    """A run whose state is NaN, batched with a healthy one of another size:
+    the healthy run is bitwise what it is alone; the bad one stays NaN."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2502_17805_amd import sdmhd as sd
+    good_m, bad_m = sd.shell(2, 1, 5), sd.shell(3, 1, 5)
+    bg = inp.Background(3.0)
+    Qg, Qb = inp.shell_state(good_m.x_sp, bg, 3), inp.shell_state(bad_m.x_sp, bg, 4)
+    Qb[2, 4, 17] = np.nan
+    pr = inp.run_params(3, bg)
+    pr.update(c_h=1.0, glm_a=3.0)
+    dt = 1e-3
+    nb = C.c_size_t()
+    sd._check(sd._lib.sdm_batch_workspace_size(2, C.byref(nb)))
+    bws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    prm = [sd.make_params(**pr), sd.make_params(**pr)]
+    alone = sd.Solver(good_m)
+    alone.set_state(Qg)
+    mixed, bad = sd.Solver(good_m), sd.Solver(bad_m)
+    mixed.set_state(Qg)
+    bad.set_state(Qb)
+    for _ in range(2):
+        _batch_step(sd, [alone], prm[:1], dt, bws, nb.value, stream)
+        _batch_step(sd, [mixed, bad], prm, dt, bws, nb.value, stream)
+    torch.cuda.synchronize()
+    assert torch.equal(alone.state, mixed.state)
+    assert torch.isfinite(alone.state).all() and not torch.isfinite(bad.state).all()
+
+
+def test_batch_rejects_mixed_degrees(srv):
+    import ctypes as C
+
+    import torch
+
+    from paper_2502_17805_amd import sdmhd as sd
+    a, b = sd.Solver(sd.shell(2, 1, 3)), sd.Solver(sd.shell(2, 1, 5))
+    nb = C.c_size_t()
+    sd._check(sd._lib.sdm_batch_workspace_size(2, C.byref(nb)))
+    bws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    prm = sd.make_params(c_h=1.0)
+    st = sd.Stage()
+    st.n_in, st.in_idx[0], st.alpha[0], st.cur, st.out, st.beta = 1, 0, 1.0, 0, 1, 0.5
+    items = (sd.BatchItem * 2)()
+    for k, s in enumerate((a, b)):
+        regs = (C.c_void_p * 4)(*[r.data_ptr() for r in s.regs])
+        items[k] = sd.BatchItem(s._h.value, C.pointer(prm), regs, 4, st, 1e-3, s.ws.data_ptr())
+    rc = sd._lib.sdm_batch_stage(items, 2, bws.data_ptr(), nb.value, 0,
+                                 C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc != sd.SDM_OK and b"share p" in sd._lib.sdm_last_error()
