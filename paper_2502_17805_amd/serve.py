@@ -167,14 +167,19 @@ class Server:
     """Admission by slots and HBM budget; one batched SSPRK step per iteration."""
 
     def __init__(self, budget_bytes: float = 200e9, max_slots: int = 64, device: int = 0, max_blocks: int = 0,
-                 keep_states=False):
+                 keep_states=False, max_elements: int = 0):
         """keep_states: True (all), a set of request ids, or False: whose
-        final states are copied back with their results."""
+        final states are copied back with their results.  max_elements > 0
+        caps the elements resident at once (admission waits while the cap
+        would be exceeded, except for a request that is alone): enough
+        elements keep every CU busy, more only lengthen every resident
+        request's latency."""
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
         self.budget = budget_bytes
         self.max_slots = max_slots
+        self.max_elements = max_elements
         self.max_blocks = max_blocks
         self.keep_states = keep_states
         self.cache = _MeshCache(self.device)
@@ -219,7 +224,10 @@ class Server:
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now and len(active) < self.max_slots:
                 q = pending[0]
-                if used + request_bytes(q) > self.budget:
+                E_q = 6 * q.Nz * q.Nz * q.Nr
+                over_elems = self.max_elements > 0 and active and \
+                    sum(6 * r.req.Nz * r.req.Nz * r.req.Nr for r in active) + E_q > self.max_elements
+                if used + request_bytes(q) > self.budget or over_elems:
                     queued_wait += 1
                     break
                 pending.popleft()
@@ -291,10 +299,12 @@ def main(argv=None):
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--identity", type=int, default=3)
+    ap.add_argument("--max-elements", type=int, default=32768,
+                    help="cap on resident elements (0: none); see Server")
     a = ap.parse_args(argv)
     reqs = poisson_requests(a.requests, a.mean_gap, a.steps, arith=a.arith)
     ids = set(range(min(a.identity, len(reqs))))
-    srv = Server(budget_bytes=a.budget_gb * 1e9, max_slots=a.slots, keep_states=ids)
+    srv = Server(budget_bytes=a.budget_gb * 1e9, max_slots=a.slots, keep_states=ids, max_elements=a.max_elements)
     res, st = srv.run(reqs)
     same = []
     for i in sorted(ids):
@@ -303,6 +313,7 @@ def main(argv=None):
     out = dict(workload=f"{a.requests} requests, Poisson arrivals (mean gap {a.mean_gap * 1e3:g} ms), shells "
                         f"6x{{4,8,12}}^2x{{3,4,8}}, p in {{3,5}}, N_rho in {{3,5}}, {a.steps} SSPRK(5,3) steps each",
                arith="fp64" if a.arith == 0 else "fp32-mixed", budget_gb=a.budget_gb, slots=a.slots,
+               max_elements=a.max_elements,
                nan_results=int(sum(r.diag[8] != 0 for r in res)), alone_vs_mix_bitwise=same, **st)
     print(json.dumps(out), flush=True)
 
