@@ -216,35 +216,27 @@ constexpr int block_threads() {
   return ((N * N * N + 63) / 64) * 64 < 64 ? 64 : ((N * N * N + 63) / 64) * 64;
 }
 
-// Position of solution point x inside an LDS field block of k_volume.  For
-// even N the two doubles of each pair swap places when bit 4 of x is set:
-// the accesses at a stride of N = 6 doubles (lines along the first
-// reference direction, read across consecutive lanes) then fall in 16
-// distinct 8-byte bank pairs instead of 8.
-template <int N>
-__device__ __forceinline__ int swz(int x) {
-  if constexpr ((N & 1) == 0) return x ^ ((x >> 4) & 1);
-  return x;
+// ---------------------------------------------------------------------------
+// interpolation of the solution-point fields to one flux point
+// ---------------------------------------------------------------------------
+// k_volume keeps Q and grad_x Q of its element in LDS point by point: row sp
+// of `RS` values holds Q (0..8), then the gradient (9 + 3 v + c: component c
+// of variable v), then padding; a point's 36 fields are contiguous, so one
+// 16-byte LDS read fetches two of them.  RS = 38 doubles (row 304 B: rows of
+// 8 consecutive points fall in distinct banks) or 36 floats.
+template <typename T>
+constexpr int row_stride() {
+  return sizeof(T) == 8 ? 38 : 36;
 }
 
-// ---------------------------------------------------------------------------
-// interpolation of one solution-point field along a line to one flux point
-// ---------------------------------------------------------------------------
+// Q and grad_x Q at one flux point from the point rows: one pass over the
+// line's N solution points accumulating all 36 fields; w[i * ws] are the
+// interpolation weights; optionally the radiative diffusivity sampled at
+// the SPs and interpolated the same way.
 template <int N, typename T>
-__device__ __forceinline__ T line_interp(const T* f, const T* w, int s0, int st) {
-  T s = T(0);
-#pragma unroll
-  for (int i = 0; i < N; ++i) s += w[i] * f[swz<N>(s0 + i * st)];
-  return s;
-}
-
-// Q and grad_x Q at one flux point: one pass over the line's N solution
-// points accumulating all 36 fields (bounded live state); optionally the
-// radiative diffusivity sampled at the SPs and interpolated the same way.
-template <int N, typename T>
-__device__ __forceinline__ T interp_point(const T* sQ, const T* sG, const T* w, int s0, int st, T qf[9],
-                                          T gf[27], bool use_kr, const Run<T>& R) {
-  constexpr int N3 = N * N * N;
+__device__ __forceinline__ T interp_rows(const T* sR, const T* w, int ws, int s0, int st, T qf[9], T gf[27],
+                                         bool use_kr, const Run<T>& R) {
+  constexpr int N3 = N * N * N, RS = row_stride<T>();
 #pragma unroll
   for (int v = 0; v < 9; ++v) qf[v] = T(0);
 #pragma unroll
@@ -252,12 +244,32 @@ __device__ __forceinline__ T interp_point(const T* sQ, const T* sG, const T* w, 
   T kf = T(0);
 #pragma unroll 1
   for (int i = 0; i < N; ++i) {
-    const T wi = w[i];
-    const int sidx = s0 + i * st, lidx = swz<N>(sidx);
+    const T wi = w[i * ws];
+    const int sidx = s0 + i * st;
+    T a[36];  // the row's 36 fields, 16 bytes per LDS read
+    if constexpr (sizeof(T) == 8) {
+      const double2* row = reinterpret_cast<const double2*>(sR + sidx * RS);
 #pragma unroll
-    for (int v = 0; v < 9; ++v) qf[v] += wi * sQ[v * N3 + lidx];
+      for (int j = 0; j < 18; ++j) {
+        const double2 x = row[j];
+        a[2 * j] = x.x;
+        a[2 * j + 1] = x.y;
+      }
+    } else {
+      const float4* row = reinterpret_cast<const float4*>(sR + sidx * RS);
 #pragma unroll
-    for (int k = 0; k < 27; ++k) gf[k] += wi * sG[k * N3 + lidx];
+      for (int j = 0; j < 9; ++j) {
+        const float4 x = row[j];
+        a[4 * j] = x.x;
+        a[4 * j + 1] = x.y;
+        a[4 * j + 2] = x.z;
+        a[4 * j + 3] = x.w;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 9; ++v) qf[v] += wi * a[v];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) gf[k] += wi * a[9 + k];
     if (use_kr) {
       const T x[3] = {(T)R.x_sp[(R.e * 3 + 0) * N3 + sidx], (T)R.x_sp[(R.e * 3 + 1) * N3 + sidx],
                       (T)R.x_sp[(R.e * 3 + 2) * N3 + sidx]};
@@ -308,11 +320,11 @@ __device__ __forceinline__ void load_outside(const Run<T>& R, int f, int ab, int
 // the wave) are staged once per workgroup in LDS: I [N+1][N], D [N][N+1]
 // ---------------------------------------------------------------------------
 template <int N, typename T>
-__device__ __forceinline__ void stage_tables(T* sI, T* sD) {
+__device__ __forceinline__ void stage_tables(T* sI, T* sD, int is = 1, int ds = 1) {
   const DevTab<T>& tb = tab<T>(N);
   for (int i = threadIdx.x; i < (N + 1) * N; i += blockDim.x) {
-    sI[i] = tb.I[i / N][i % N];
-    sD[i] = tb.D[i / (N + 1)][i % (N + 1)];
+    sI[i * is] = tb.I[i / N][i % N];
+    sD[i * ds] = tb.D[i / (N + 1)][i % (N + 1)];
   }
 }
 
@@ -374,11 +386,18 @@ void k_volume(Launch L) {
   // when one pass covers them all
   constexpr bool FACE_REG = 6 * N2 <= BS;
   constexpr bool INT_REG = NI <= BS;
-  __shared__ T sQ[9 * N3];
-  __shared__ T sG[27 * N3];
+  // the element's point rows (Q, then grad_x Q); FP64 rows have two spare
+  // slots, where the basis tables live (I in slot 36, D in slot 37)
+  constexpr int RS = row_stride<T>();
+  constexpr bool PADTAB = RS >= 38;
+  static_assert(!PADTAB || (N + 1) * N <= N3, "tables fit the spare slots");
+  __shared__ __align__(16) T sR[N3 * RS];
   __shared__ T sU[UN];  // face jumps (common value - own trace), then fluxes
   __shared__ double sRed[BS / 64][10];
-  __shared__ T sI[(N + 1) * N], sD[N * (N + 1)];
+  __shared__ T sIa[PADTAB ? 1 : (N + 1) * N], sDa[PADTAB ? 1 : N * (N + 1)];
+  T* const sI = PADTAB ? sR + 36 : sIa;
+  T* const sD = PADTAB ? sR + 37 : sDa;
+  constexpr int is = PADTAB ? RS : 1, ds = PADTAB ? RS : 1;
   // the physical parameters, read from LDS where they are used: held in
   // scalar registers for the whole element they overflow them
   __shared__ Phys<T> sP;
@@ -405,7 +424,7 @@ void k_volume(Launch L) {
     //    LDS; the chain-rule factors and position of this thread's SP; the
     //    outside state and normal of this thread's face point; the metric at
     //    this thread's interior flux points of the three families.
-    for (int i = tid; i < 9 * N3; i += BS) sQ[i - i % N3 + swz<N>(i % N3)] = (T)Qe[i];
+    for (int i = tid; i < 9 * N3; i += BS) sR[(i % N3) * RS + i / N3] = (T)Qe[i];
     T ji = T(0), Sj[3][3], xs[3] = {T(0), T(0), T(0)};
     if (tid < N3) {
       ji = recip((T)R.detJ[e * N3 + tid]);
@@ -433,18 +452,23 @@ void k_volume(Launch L) {
         for (int c = 0; c < 3; ++c) Sint[d][c] = (T)Se[(d * 3 + c) * NF + fi];
       }
     }
-    stage_tables<N>(sI, sD);  // after the element's loads are in flight
+    stage_tables<N>(sI, sD, is, ds);  // after the element's loads are in flight
     __syncthreads();
 
     // B. BR1 common solution at the 6 N^2 face points, stored as the jump
     //    (common value - own trace) that the gradient correction uses.
-    //    B1: own traces into the (still unused) gradient buffer sG.
-    T* sTr = sG;  // [6][9][N2]
+    //    B1: own traces [6][9][N2] into the (still unused) gradient slots
+    //    of the point rows, entry t at row t / 27, slot 9 + t % 27.
     for (int it = tid; it < 6 * 9 * N2; it += BS) {
       const int ab = it % N2, fv = it / N2, v = fv % 9, f = fv / 9;
       const int d = f >> 1;
       const int st = d == 0 ? 1 : (d == 1 ? N : N2);
-      sTr[it] = line_interp<N>(sQ + v * N3, sI + ((f & 1) ? N : 0) * N, sp_line<N>(d, ab % N, ab / N, 0), st);
+      const int s0 = sp_line<N>(d, ab % N, ab / N, 0);
+      const T* wI = sI + ((f & 1) ? N : 0) * N * is;
+      T acc = T(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc += wI[i * is] * sR[(s0 + i * st) * RS + v];
+      sR[(it / 27) * RS + 9 + it % 27] = acc;
     }
     __syncthreads();
     //    B2: jumps from the own and the outside (neighbour, wall or ghost) state
@@ -461,16 +485,19 @@ void k_volume(Launch L) {
         code = nb6[f];
         load_outside<N>(R, f, ab, code, q_out, n);
       }
-      const T* own = sTr + f * 9 * N2 + ab;
+      const int t0 = f * 9 * N2 + ab;  // this point's own traces: t0 + v N2
+      T own[9];
+#pragma unroll
+      for (int v = 0; v < 9; ++v) own[v] = sR[((t0 + v * N2) / 27) * RS + 9 + (t0 + v * N2) % 27];
       T* dst = sU + f * 9 * N2 + ab;
       const int g = code >= 0 ? -1 : ((-code - 1) & 3);
       if (code >= 0 || g >= 2 || wsel(g, P.wall_kind) == 1) {
 #pragma unroll
-        for (int v = 0; v < 9; ++v) dst[v * N2] = T(0.5) * (q_out[v] - own[v * N2]);
+        for (int v = 0; v < 9; ++v) dst[v * N2] = T(0.5) * (q_out[v] - own[v]);
       } else {
         T qo[9], qc[9];
 #pragma unroll
-        for (int v = 0; v < 9; ++v) qo[v] = own[v * N2];
+        for (int v = 0; v < 9; ++v) qo[v] = own[v];
         const T inn = recip(sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]));
         const T nh[3] = {n[0] * inn, n[1] * inn, n[2] * inn};
         wall_common(qo, nh, g, P, qc);
@@ -484,16 +511,17 @@ void k_volume(Launch L) {
     //    C1: derivative of each variable along each line: the solution
     //    polynomial's own derivative plus the lifting of the two end jumps;
     //    one (direction, line, variable) per thread, point index uniform so
-    //    the table entries are scalar loads.  Written to sG as dQ/dxi_d.
+    //    the table entries are scalar loads.  Written to the gradient slots
+    //    of the point rows as dQ/dxi_d.
     for (int it = tid; it < 3 * 9 * N2; it += BS) {
       const int pq = it % N2, dv = it / N2, v = dv % 9, d = dv / 9;
       const int st = d == 0 ? 1 : (d == 1 ? N : N2);
       const int s0 = sp_line<N>(d, pq % N, pq / N, 0);
       T ln[N];
 #pragma unroll
-      for (int j = 0; j < N; ++j) ln[j] = sQ[v * N3 + swz<N>(s0 + j * st)];
+      for (int j = 0; j < N; ++j) ln[j] = sR[(s0 + j * st) * RS + v];
       const T j0 = sU[((2 * d) * 9 + v) * N2 + pq], jN = sU[((2 * d + 1) * 9 + v) * N2 + pq];
-      T* out = sG + (v * 3 + d) * N3;
+      T* out = sR + 9 + v * 3 + d;
       // one row of the tables per step (scalar loads), not all N^2 + 2N
       // entries held in scalar registers at once
 #pragma unroll 1
@@ -501,7 +529,7 @@ void k_volume(Launch L) {
         T dd = tb.D[i][0] * j0 + tb.D[i][N] * jN;
 #pragma unroll
         for (int j = 0; j < N; ++j) dd += tb.DI[i][j] * ln[j];
-        out[swz<N>(s0 + i * st)] = dd;
+        out[(s0 + i * st) * RS] = dd;
       }
     }
     __syncthreads();
@@ -510,10 +538,10 @@ void k_volume(Launch L) {
     if (tid < N3) {
 #pragma unroll
       for (int v = 0; v < 9; ++v) {
-        T* g = sG + v * 3 * N3 + swz<N>(tid);
-        const T d0 = g[0], d1 = g[N3], d2 = g[2 * N3];
+        T* g = sR + tid * RS + 9 + v * 3;
+        const T d0 = g[0], d1 = g[1], d2 = g[2];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) g[c * N3] = Sj[0][c] * d0 + Sj[1][c] * d1 + Sj[2][c] * d2;
+        for (int c = 0; c < 3; ++c) g[c] = Sj[0][c] * d0 + Sj[1][c] * d1 + Sj[2][c] * d2;
       }
     }
     __syncthreads();
@@ -528,8 +556,8 @@ void k_volume(Launch L) {
         const double rho = q[0];
         const double m2 = q[N3] * q[N3] + q[2 * N3] * q[2 * N3] + q[3 * N3] * q[3 * N3];
         const double b2 = q[5 * N3] * q[5 * N3] + q[6 * N3] * q[6 * N3] + q[7 * N3] * q[7 * N3];
-        const int sx = swz<N>(sp);
-        const double db = (double)sG[15 * N3 + sx] + (double)sG[19 * N3 + sx] + (double)sG[23 * N3 + sx];
+        const T* row = sR + sp * RS;
+        const double db = (double)row[24] + (double)row[28] + (double)row[32];
         acc[0] = wq;
         acc[1] = wq * rho;
         acc[2] = wq * q[4 * N3];
@@ -578,7 +606,7 @@ void k_volume(Launch L) {
       const int st = d == 0 ? 1 : (d == 1 ? N : N2);
       const int s0 = sp_line<N>(d, p, q, 0);
       T qf[9], gf[27];
-      T kf = interp_point<N>(sQ, sG, sI + fe * N, s0, st, qf, gf, use_kr, R);
+      T kf = interp_rows<N>(sR, sI + fe * N * is, is, s0, st, qf, gf, use_kr, R);
       T qx[9], n[3];
       int32_t code;
       if (FACE_REG) {
@@ -640,7 +668,7 @@ void k_volume(Launch L) {
       for (int d = 0; d < 3; ++d) {
         const int p = d == 0 ? ia1 : ia0, q = d == 2 ? ia1 : ia2, i = d == 0 ? ia0 : (d == 1 ? ia1 : ia2);
         const int pq = p + N * q;
-        const T d0 = sD[i * NP], dN = sD[i * NP + N];
+        const T d0 = sD[(i * NP) * ds], dN = sD[(i * NP + N) * ds];
 #pragma unroll
         for (int v = 0; v < 9; ++v)
           div[v] += d0 * sU[((2 * d) * 9 + v) * N2 + pq] + dN * sU[((2 * d + 1) * 9 + v) * N2 + pq];
@@ -656,7 +684,7 @@ void k_volume(Launch L) {
         const int p = line % N, q = line / N;
         const int s0 = sp_line<N>(d, p, q, 0);
         T qf[9], gf[27];
-        T kf = interp_point<N>(sQ, sG, sI + f * N, s0, st, qf, gf, use_kr, R);
+        T kf = interp_rows<N>(sR, sI + f * N * is, is, s0, st, qf, gf, use_kr, R);
         T Sd[3];
         if (INT_REG) {
           Sd[0] = Sint[d][0]; Sd[1] = Sint[d][1]; Sd[2] = Sint[d][2];
@@ -681,7 +709,7 @@ void k_volume(Launch L) {
         const int base = (p + N * q) * (N - 1);
 #pragma unroll 1
         for (int f = 1; f < N; ++f) {
-          const T df = sD[i * NP + f];
+          const T df = sD[(i * NP + f) * ds];
 #pragma unroll
           for (int v = 0; v < 9; ++v) div[v] += df * sU[v * NI + base + f - 1];
         }
@@ -694,7 +722,7 @@ void k_volume(Launch L) {
       const int sp = tid;
       T q[9];
 #pragma unroll
-      for (int v = 0; v < 9; ++v) q[v] = sQ[v * N3 + swz<N>(sp)];
+      for (int v = 0; v < 9; ++v) q[v] = sR[sp * RS + v];
       T gv[3] = {T(0), T(0), T(0)};
       if (P.GM != T(0)) {
         const T r2 = xs[0] * xs[0] + xs[1] * xs[1] + xs[2] * xs[2];
@@ -702,8 +730,8 @@ void k_volume(Launch L) {
         gv[0] = sc * xs[0]; gv[1] = sc * xs[1]; gv[2] = sc * xs[2];
       }
       const T ir = recip(q[0]);
-      const int sx = swz<N>(sp);
-      const T db = P.powell ? sG[15 * N3 + sx] + sG[19 * N3 + sx] + sG[23 * N3 + sx] : T(0);
+      const T* row = sR + sp * RS;
+      const T db = P.powell ? row[24] + row[28] + row[32] : T(0);
       const T uB = (q[1] * q[5] + q[2] * q[6] + q[3] * q[7]) * ir;
       T M[9];
       M[0] = T(0);
