@@ -457,10 +457,12 @@ void k_volume(Launch L) {
 
     // B. BR1 common solution at the 6 N^2 face points, stored as the jump
     //    (common value - own trace) that the gradient correction uses.
-    //    B1: own traces [6][9][N2] into the (still unused) gradient slots
-    //    of the point rows, entry t at row t / 27, slot 9 + t % 27.
+    //    B1: own traces into the (still unused) gradient slots of the point
+    //    rows: the 9 values of face point pt = f N2 + ab at row pt / 3,
+    //    slots 9 + 9 (pt % 3) + v.  Variable fastest across lanes, so lanes
+    //    read neighbouring slots of the same rows.
     for (int it = tid; it < 6 * 9 * N2; it += BS) {
-      const int ab = it % N2, fv = it / N2, v = fv % 9, f = fv / 9;
+      const int v = it % 9, pt = it / 9, ab = pt % N2, f = pt / N2;
       const int d = f >> 1;
       const int st = d == 0 ? 1 : (d == 1 ? N : N2);
       const int s0 = sp_line<N>(d, ab % N, ab / N, 0);
@@ -468,7 +470,7 @@ void k_volume(Launch L) {
       T acc = T(0);
 #pragma unroll
       for (int i = 0; i < N; ++i) acc += wI[i * is] * sR[(s0 + i * st) * RS + v];
-      sR[(it / 27) * RS + 9 + it % 27] = acc;
+      sR[(pt / 3) * RS + 9 + 9 * (pt % 3) + v] = acc;
     }
     __syncthreads();
     //    B2: jumps from the own and the outside (neighbour, wall or ghost) state
@@ -485,10 +487,10 @@ void k_volume(Launch L) {
         code = nb6[f];
         load_outside<N>(R, f, ab, code, q_out, n);
       }
-      const int t0 = f * 9 * N2 + ab;  // this point's own traces: t0 + v N2
+      const T* tr = sR + (it / 3) * RS + 9 + 9 * (it % 3);  // this point's own traces
       T own[9];
 #pragma unroll
-      for (int v = 0; v < 9; ++v) own[v] = sR[((t0 + v * N2) / 27) * RS + 9 + (t0 + v * N2) % 27];
+      for (int v = 0; v < 9; ++v) own[v] = tr[v];
       T* dst = sU + f * 9 * N2 + ab;
       const int g = code >= 0 ? -1 : ((-code - 1) & 3);
       if (code >= 0 || g >= 2 || wsel(g, P.wall_kind) == 1) {
@@ -514,7 +516,7 @@ void k_volume(Launch L) {
     //    the table entries are scalar loads.  Written to the gradient slots
     //    of the point rows as dQ/dxi_d.
     for (int it = tid; it < 3 * 9 * N2; it += BS) {
-      const int pq = it % N2, dv = it / N2, v = dv % 9, d = dv / 9;
+      const int v = it % 9, t = it / 9, pq = t % N2, d = t / N2;  // variable fastest
       const int st = d == 0 ? 1 : (d == 1 ? N : N2);
       const int s0 = sp_line<N>(d, pq % N, pq / N, 0);
       T ln[N];
