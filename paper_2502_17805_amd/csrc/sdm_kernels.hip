@@ -455,25 +455,10 @@ void k_volume(Launch L) {
     stage_tables<N>(sI, sD, is, ds);  // after the element's loads are in flight
     __syncthreads();
 
-    // B. BR1 common solution at the 6 N^2 face points, stored as the jump
-    //    (common value - own trace) that the gradient correction uses.
-    //    B1: own traces into the (still unused) gradient slots of the point
-    //    rows: the 9 values of face point pt = f N2 + ab at row pt / 3,
-    //    slots 9 + 9 (pt % 3) + v.  Variable fastest across lanes, so lanes
-    //    read neighbouring slots of the same rows.
-    for (int it = tid; it < 6 * 9 * N2; it += BS) {
-      const int v = it % 9, pt = it / 9, ab = pt % N2, f = pt / N2;
-      const int d = f >> 1;
-      const int st = d == 0 ? 1 : (d == 1 ? N : N2);
-      const int s0 = sp_line<N>(d, ab % N, ab / N, 0);
-      const T* wI = sI + ((f & 1) ? N : 0) * N * is;
-      T acc = T(0);
-#pragma unroll
-      for (int i = 0; i < N; ++i) acc += wI[i * is] * sR[(s0 + i * st) * RS + v];
-      sR[(pt / 3) * RS + 9 + 9 * (pt % 3) + v] = acc;
-    }
-    __syncthreads();
-    //    B2: jumps from the own and the outside (neighbour, wall or ghost) state
+    // B. BR1 common solution at the 6 N^2 face points (one per thread): the
+    //    own trace, and the common value from the outside (neighbour, wall or
+    //    ghost) state, stored as the jump (common value - own trace) that
+    //    the gradient correction uses.
     for (int it = tid; it < 6 * N2; it += BS) {
       const int f = it / N2, ab = it % N2;
       T q_out[9], n[3];
@@ -487,10 +472,21 @@ void k_volume(Launch L) {
         code = nb6[f];
         load_outside<N>(R, f, ab, code, q_out, n);
       }
-      const T* tr = sR + (it / 3) * RS + 9 + 9 * (it % 3);  // this point's own traces
+      // the own trace: Q interpolated along the line to the face
+      const int d = f >> 1;
+      const int st = d == 0 ? 1 : (d == 1 ? N : N2);
+      const int s0 = sp_line<N>(d, ab % N, ab / N, 0);
+      const T* wI = sI + ((f & 1) ? N : 0) * N * is;
       T own[9];
 #pragma unroll
-      for (int v = 0; v < 9; ++v) own[v] = tr[v];
+      for (int v = 0; v < 9; ++v) own[v] = T(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const T wi = wI[i * is];
+        const T* row = sR + (s0 + i * st) * RS;
+#pragma unroll
+        for (int v = 0; v < 9; ++v) own[v] += wi * row[v];
+      }
       T* dst = sU + f * 9 * N2 + ab;
       const int g = code >= 0 ? -1 : ((-code - 1) & 3);
       if (code >= 0 || g >= 2 || wsel(g, P.wall_kind) == 1) {
