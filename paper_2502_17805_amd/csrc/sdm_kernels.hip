@@ -392,7 +392,7 @@ void k_volume(Launch L) {
   constexpr bool PADTAB = RS >= 38;
   static_assert(!PADTAB || (N + 1) * N <= N3, "tables fit the spare slots");
   __shared__ __align__(16) T sR[N3 * RS];
-  __shared__ T sU[UN];  // face jumps (common value - own trace), then fluxes
+  __shared__ T sU[UN];  // face jumps (common value - own trace), then fluxes: 9 per point
   __shared__ double sRed[BS / 64][10];
   __shared__ T sIa[PADTAB ? 1 : (N + 1) * N], sDa[PADTAB ? 1 : N * (N + 1)];
   T* const sI = PADTAB ? sR + 36 : sIa;
@@ -487,11 +487,11 @@ void k_volume(Launch L) {
 #pragma unroll
         for (int v = 0; v < 9; ++v) own[v] += wi * row[v];
       }
-      T* dst = sU + f * 9 * N2 + ab;
+      T* dst = sU + it * 9;
       const int g = code >= 0 ? -1 : ((-code - 1) & 3);
       if (code >= 0 || g >= 2 || wsel(g, P.wall_kind) == 1) {
 #pragma unroll
-        for (int v = 0; v < 9; ++v) dst[v * N2] = T(0.5) * (q_out[v] - own[v]);
+        for (int v = 0; v < 9; ++v) dst[v] = T(0.5) * (q_out[v] - own[v]);
       } else {
         T qo[9], qc[9];
 #pragma unroll
@@ -500,7 +500,7 @@ void k_volume(Launch L) {
         const T nh[3] = {n[0] * inn, n[1] * inn, n[2] * inn};
         wall_common(qo, nh, g, P, qc);
 #pragma unroll
-        for (int v = 0; v < 9; ++v) dst[v * N2] = qc[v] - qo[v];
+        for (int v = 0; v < 9; ++v) dst[v] = qc[v] - qo[v];
       }
     }
     __syncthreads();
@@ -518,7 +518,7 @@ void k_volume(Launch L) {
       T ln[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) ln[j] = sR[(s0 + j * st) * RS + v];
-      const T j0 = sU[((2 * d) * 9 + v) * N2 + pq], jN = sU[((2 * d + 1) * 9 + v) * N2 + pq];
+      const T j0 = sU[((2 * d) * N2 + pq) * 9 + v], jN = sU[((2 * d + 1) * N2 + pq) * 9 + v];
       T* out = sR + 9 + v * 3 + d;
       // one row of the tables per step (scalar loads), not all N^2 + 2N
       // entries held in scalar registers at once
@@ -658,7 +658,7 @@ void k_volume(Launch L) {
       // the flux polynomial of family d takes -F at its coordinate 0, +F at 1
       const T sg = (face & 1) ? T(1) : T(-1);
 #pragma unroll
-      for (int v = 0; v < 9; ++v) sU[(face * 9 + v) * N2 + ab] = sg * F[v];
+      for (int v = 0; v < 9; ++v) sU[it * 9 + v] = sg * F[v];
     }
     __syncthreads();
     if (tid < N3) {
@@ -669,7 +669,7 @@ void k_volume(Launch L) {
         const T d0 = sD[(i * NP) * ds], dN = sD[(i * NP + N) * ds];
 #pragma unroll
         for (int v = 0; v < 9; ++v)
-          div[v] += d0 * sU[((2 * d) * 9 + v) * N2 + pq] + dN * sU[((2 * d + 1) * 9 + v) * N2 + pq];
+          div[v] += d0 * sU[((2 * d) * N2 + pq) * 9 + v] + dN * sU[((2 * d + 1) * N2 + pq) * 9 + v];
       }
     }
     __syncthreads();
@@ -699,7 +699,7 @@ void k_volume(Launch L) {
 #pragma unroll
         for (int c = 0; c < 7; ++c) F[1 + c] -= Fv[c];
 #pragma unroll
-        for (int v = 0; v < 9; ++v) sU[v * NI + it] = F[v];
+        for (int v = 0; v < 9; ++v) sU[it * 9 + v] = F[v];
       }
       __syncthreads();
       if (tid < N3) {
@@ -709,7 +709,7 @@ void k_volume(Launch L) {
         for (int f = 1; f < N; ++f) {
           const T df = sD[(i * NP + f) * ds];
 #pragma unroll
-          for (int v = 0; v < 9; ++v) div[v] += df * sU[v * NI + base + f - 1];
+          for (int v = 0; v < 9; ++v) div[v] += df * sU[(base + f - 1) * 9 + v];
         }
       }
       __syncthreads();
