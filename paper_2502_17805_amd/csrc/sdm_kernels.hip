@@ -44,7 +44,6 @@ template <typename T>
 struct DevTab {
   T I[kNMax + 1][kNMax];   // SP basis at FPs
   T D[kNMax][kNMax + 1];   // FP-basis derivative at SPs
-  T L[kNMax][kNMax + 1];   // FP basis at SPs
   T DI[kNMax][kNMax];      // derivative of the SP polynomial at SPs
   T W[kNMax];              // quadrature weights
 };
@@ -936,10 +935,7 @@ sdm_status upload_tables(int device) {
     for (int f = 0; f <= N; ++f)
       for (int i = 0; i < N; ++i) td[N].I[f][i] = t.I[f * N + i];
     for (int i = 0; i < N; ++i)
-      for (int f = 0; f <= N; ++f) {
-        td[N].D[i][f] = t.D[i * (N + 1) + f];
-        td[N].L[i][f] = t.L[i * (N + 1) + f];
-      }
+      for (int f = 0; f <= N; ++f) td[N].D[i][f] = t.D[i * (N + 1) + f];
     for (int i = 0; i < N; ++i)
       for (int j = 0; j < N; ++j) td[N].DI[i][j] = t.DI[i * N + j];
     for (int i = 0; i < N; ++i) td[N].W[i] = t.W[i];
