@@ -34,6 +34,7 @@ CONFIGS = {  # name: (Nz, Nr, p, N_rho, seed)
     "shell_55296_p5": (24, 16, 5, 5.0, 2),
     "shell_6912_p5": (12, 8, 5, 3.0, 1),
     "shell_48_p5": (2, 2, 5, 3.0, 0),
+    "shell_55296_p3": (24, 16, 3, 5.0, 2),
 }
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
