@@ -208,6 +208,21 @@ typedef struct {
 sdm_status sdm_rk_stage(sdm_ctx* ctx, const sdm_params* prm, double* const* regs, int n_regs,
                         const sdm_stage* stage, double dt, void* ws, void* stream);
 
+/* The two halves of sdm_rk_stage, for a mesh split over several GPUs: the
+ * volume half (face traces of regs[cur] unless traces_valid, then every
+ * element's residual except the neighbour half of the viscous flux; it
+ * reads import_q and leaves this partition's viscous face fluxes in `ws`,
+ * see sdm_workspace_traces) and the finish half (the neighbour half, read
+ * from import_v on import faces, and the Shu-Osher update; it leaves the
+ * new state's face traces in `ws`).  A split run exchanges the Q traces
+ * before the volume half and the viscous fluxes between the halves.  Same
+ * arguments as sdm_rk_stage; volume followed by finish equals sdm_rk_stage
+ * bitwise. */
+sdm_status sdm_rk_stage_volume(sdm_ctx* ctx, const sdm_params* prm, double* const* regs, int n_regs,
+                               const sdm_stage* stage, double dt, void* ws, void* stream);
+sdm_status sdm_rk_stage_finish(sdm_ctx* ctx, const sdm_params* prm, double* const* regs, int n_regs,
+                               const sdm_stage* stage, double dt, void* ws, void* stream);
+
 /* Diagnostics of state Q into DEVICE out[16] (FP64): volume, mass, total
  * energy, volume-averaged KE = (1/V) int rho|u|^2/2, E_B = (1/V) int
  * |B|^2/2 (Sec. "Results"), max|div B|, L2 norm of div B, max|psi|, NaN/Inf

@@ -1353,16 +1353,20 @@ sdm_status sdm_residual(sdm_ctx* c, const sdm_params* p, const double* Q, double
   return run(c, 3, L, s);
 }
 
-sdm_status sdm_rk_stage(sdm_ctx* c, const sdm_params* p, double* const* regs, int n_regs,
-                        const sdm_stage* stg, double dt, void* ws, void* stream) {
-  if (!c || !regs || !stg || !ws) return fail(SDM_EINVAL, "rk_stage: NULL argument");
-  if (!c->bound) return fail(SDM_ESTATE, "rk_stage: no mesh bound");
-  if (n_regs < 1 || n_regs > 16) return fail(SDM_EINVAL, "rk_stage: 1 <= n_regs <= 16");
-  if (stg->n_in < 0 || stg->n_in > 4) return fail(SDM_EINVAL, "rk_stage: 0 <= n_in <= 4");
+namespace {
+// the launches of one stage: `parts` bit 0 = traces (unless valid) and
+// volume, bit 1 = finish (neighbour viscous half + Shu-Osher update)
+sdm_status stage_parts(sdm_ctx* c, const sdm_params* p, double* const* regs, int n_regs, const sdm_stage* stg,
+                       double dt, void* ws, void* stream, int parts, const char* who) {
+  if (!c || !regs || !stg || !ws) return fail(SDM_EINVAL, std::string(who) + ": NULL argument");
+  if (!c->bound) return fail(SDM_ESTATE, std::string(who) + ": no mesh bound");
+  if (n_regs < 1 || n_regs > 16) return fail(SDM_EINVAL, std::string(who) + ": 1 <= n_regs <= 16");
+  if (stg->n_in < 0 || stg->n_in > 4) return fail(SDM_EINVAL, std::string(who) + ": 0 <= n_in <= 4");
   auto okreg = [&](int i) { return i >= 0 && i < n_regs && regs[i] != nullptr; };
-  if (!okreg(stg->cur) || !okreg(stg->out)) return fail(SDM_EINVAL, "rk_stage: register index out of range");
+  if (!okreg(stg->cur) || !okreg(stg->out))
+    return fail(SDM_EINVAL, std::string(who) + ": register index out of range");
   for (int k = 0; k < stg->n_in; ++k)
-    if (!okreg(stg->in_idx[k])) return fail(SDM_EINVAL, "rk_stage: input register out of range");
+    if (!okreg(stg->in_idx[k])) return fail(SDM_EINVAL, std::string(who) + ": input register out of range");
   sdm_status st = check_params(c, p);
   if (st != SDM_OK) return st;
   HIP_TRY(hipSetDevice(c->device));
@@ -1377,9 +1381,28 @@ sdm_status sdm_rk_stage(sdm_ctx* c, const sdm_params* p, double* const* regs, in
   r.beta_dt = stg->beta * dt;
   r.write_traces = 1;
   Launch L = single(r);
-  if (!stg->traces_valid && (st = run(c, 0, L, s)) != SDM_OK) return st;
-  if ((st = run(c, 1, L, s)) != SDM_OK) return st;
-  return run(c, 4, L, s);
+  if (parts & 1) {
+    if (!stg->traces_valid && (st = run(c, 0, L, s)) != SDM_OK) return st;
+    if ((st = run(c, 1, L, s)) != SDM_OK) return st;
+  }
+  if (parts & 2) return run(c, 4, L, s);
+  return SDM_OK;
+}
+}  // namespace
+
+sdm_status sdm_rk_stage(sdm_ctx* c, const sdm_params* p, double* const* regs, int n_regs,
+                        const sdm_stage* stg, double dt, void* ws, void* stream) {
+  return stage_parts(c, p, regs, n_regs, stg, dt, ws, stream, 3, "rk_stage");
+}
+
+sdm_status sdm_rk_stage_volume(sdm_ctx* c, const sdm_params* p, double* const* regs, int n_regs,
+                               const sdm_stage* stg, double dt, void* ws, void* stream) {
+  return stage_parts(c, p, regs, n_regs, stg, dt, ws, stream, 1, "rk_stage_volume");
+}
+
+sdm_status sdm_rk_stage_finish(sdm_ctx* c, const sdm_params* p, double* const* regs, int n_regs,
+                               const sdm_stage* stg, double dt, void* ws, void* stream) {
+  return stage_parts(c, p, regs, n_regs, stg, dt, ws, stream, 2, "rk_stage_finish");
 }
 
 sdm_status sdm_diagnostics(sdm_ctx* c, const sdm_params* p, const double* Q, double* out, void* ws,

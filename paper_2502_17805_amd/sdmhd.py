@@ -85,6 +85,8 @@ _lib.sdm_workspace_traces.argtypes = [_vp, _vp, C.POINTER(C.c_void_p), C.POINTER
 _lib.sdm_residual.argtypes = [_vp, C.POINTER(Params), _vp, _vp, _vp, _vp]
 _lib.sdm_rk_stage.argtypes = [_vp, C.POINTER(Params), C.POINTER(C.c_void_p), C.c_int,
                               C.POINTER(Stage), C.c_double, _vp, _vp]
+_lib.sdm_rk_stage_volume.argtypes = _lib.sdm_rk_stage.argtypes
+_lib.sdm_rk_stage_finish.argtypes = _lib.sdm_rk_stage.argtypes
 _lib.sdm_diagnostics.argtypes = [_vp, C.POINTER(Params), _vp, _vp, _vp, _vp]
 _lib.sdm_batch_workspace_size.argtypes = [C.c_int, C.POINTER(C.c_size_t)]
 _lib.sdm_batch_stage.argtypes = [C.POINTER(BatchItem), C.c_int, _vp, C.c_size_t, C.c_int, _vp]
@@ -93,14 +95,15 @@ _lib.sdm_profile_read.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int6
 for _f in ("sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes", "sdm_box_build", "sdm_tables",
            "sdm_create", "sdm_destroy", "sdm_mesh_bind", "sdm_workspace_size", "sdm_residual",
            "sdm_rk_stage", "sdm_diagnostics", "sdm_profile_enable", "sdm_profile_read",
-           "sdm_batch_workspace_size", "sdm_batch_stage", "sdm_workspace_traces"):
+           "sdm_batch_workspace_size", "sdm_batch_stage", "sdm_workspace_traces", "sdm_rk_stage_volume",
+           "sdm_rk_stage_finish"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTED = ("sdm_last_error", "sdm_version", "sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes",
             "sdm_box_build", "sdm_tables", "sdm_create", "sdm_destroy", "sdm_mesh_bind",
             "sdm_workspace_size", "sdm_residual", "sdm_rk_stage", "sdm_diagnostics",
             "sdm_profile_enable", "sdm_profile_read", "sdm_batch_workspace_size", "sdm_batch_stage",
-            "sdm_workspace_traces")
+            "sdm_workspace_traces", "sdm_rk_stage_volume", "sdm_rk_stage_finish")
 KERNELS = ("traces", "volume", "volume_diag", "finish_residual", "finish_stage")
 
 
@@ -379,7 +382,10 @@ class Solver:
         self._traces_of = None
         return R
 
-    def stage(self, prm: Params, cur: int, inputs, beta: float, out: int, dt: float, regs=None):
+    def stage(self, prm: Params, cur: int, inputs, beta: float, out: int, dt: float, regs=None, part="all"):
+        """regs[out] = sum alpha regs[in] + beta dt R(regs[cur]).  part = "all"
+        (sdm_rk_stage), or "volume" then "finish" (its two halves, with a
+        halo exchange in between for a split mesh)."""
         regs = self.regs if regs is None else regs
         st = Stage()
         st.n_in = len(inputs)
@@ -389,9 +395,12 @@ class Solver:
         st.cur, st.out, st.beta = cur, out, beta
         st.traces_valid = 1 if (self._traces_of == cur and regs is self.regs) else 0
         arr = (C.c_void_p * len(regs))(*[r.data_ptr() for r in regs])
-        _check(_lib.sdm_rk_stage(self._h, C.byref(prm), arr, len(regs), C.byref(st), dt, self.ws.data_ptr(),
-                                 self._stream()))
-        self._traces_of = out if regs is self.regs else None
+        fn = {"all": _lib.sdm_rk_stage, "volume": _lib.sdm_rk_stage_volume, "finish": _lib.sdm_rk_stage_finish}[part]
+        _check(fn(self._h, C.byref(prm), arr, len(regs), C.byref(st), dt, self.ws.data_ptr(), self._stream()))
+        if part == "volume":
+            self._traces_of = cur if regs is self.regs else None
+        else:
+            self._traces_of = out if regs is self.regs else None
 
     def step(self, prm: Params, dt: float):
         """One SSPRK(5,3) step of the state in register 0."""
