@@ -2,10 +2,10 @@
 // residual and fused Runge-Kutta stage (paper arXiv 2502.17805, Sec.
 // "Spectral Difference Method"), and the C ABI declared in include/sdmhd.h.
 //
-// One stage = three launches, one workgroup per element:
+// One stage = two launches (k_volume, k_finish), one workgroup per element;
+// k_traces runs only before a run's first stage:
 //   k_traces  Q at the two end flux points of every line = the element's face
-//             traces  (only before the first stage; afterwards the previous
-//             stage's k_finish writes them)
+//             traces (afterwards each stage's k_finish writes them)
 //   k_volume  BR1 common solution from the own and neighbour traces, gradient
 //             at the solution points (chain rule with S^d/|J|), interpolation
 //             of Q and grad Q to each flux-point family, total flux at the
@@ -19,6 +19,8 @@
 // The face coupling uses the per-element neighbour/orientation table; each
 // interior face is evaluated by both of its elements, with the symmetric face
 // normal n = (S_own - S_other)/2 so the two values are exact negatives.
+// Faces whose neighbour lives in another partition of a split mesh (import
+// faces) take the neighbour's trace and viscous flux from caller buffers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
