@@ -217,6 +217,44 @@ constexpr int block_threads() {
   return ((N * N * N + 63) / 64) * 64 < 64 ? 64 : ((N * N * N + 63) / 64) * 64;
 }
 
+// Face point (face, ab) handled by lane t of k_volume's face passes, which
+// read the N point rows of the line through each face point.  For N = 6 the
+// lanes are arranged so that the 16 lanes LDS serves together read rows in
+// 16 distinct bank groups: each direction gets a slot of 80 lanes, the two
+// opposite faces of a direction alternate (they read the same rows, which
+// LDS broadcasts), and the points of the y faces run in 4 x 2 tiles (the
+// row stride 6 of their lines would otherwise repeat bank groups).  Other N
+// use the plain order.  Returns false for lanes without a face point.
+template <int N>
+constexpr int face_lanes() {
+  return N == 6 ? 240 : 6 * N * N;
+}
+template <int N>
+__device__ __forceinline__ bool face_lane(int t, int& face, int& ab) {
+  if constexpr (N == 6) {
+    const int d = t / 80, r = t % 80;
+    if (d >= 3 || r >= 72) return false;
+    const int k = r >> 1;
+    face = 2 * d + (r & 1);
+    int a, b;
+    if (d == 1) {
+      const int blk = k >> 3, j = k & 7;
+      a = blk < 3 ? (j & 3) : 4 + (j & 1);
+      b = blk < 3 ? 2 * blk + (j >> 2) : (blk == 3 ? (j >> 1) : 4 + (j >> 1));
+    } else {
+      a = k % 6;
+      b = k / 6;
+    }
+    ab = a + 6 * b;
+    return true;
+  } else {
+    if (t >= 6 * N * N) return false;
+    face = t / (N * N);
+    ab = t % (N * N);
+    return true;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // interpolation of the solution-point fields to one flux point
 // ---------------------------------------------------------------------------
@@ -280,16 +318,22 @@ __device__ __forceinline__ T interp_rows(const T* sR, const T* w, int ws, int s0
   return kf;
 }
 
-// Outside state and outward normal at face point ab of face f: the
-// neighbour's stored trace (orientation-mapped), the ghost state on
-// Dirichlet faces; nothing on walls (their state is built from the own one).
+// Outward normal at face point ab of face f.
 template <int N, typename T>
-__device__ __forceinline__ void load_outside(const Run<T>& R, int f, int ab, int32_t code, T q[9], T n[3]) {
+__device__ __forceinline__ void load_normal(const Run<T>& R, int f, int ab, T n[3]) {
   constexpr int N2 = N * N;
   const GBL double* nf = R.n_face + (R.e * 6 + f) * 3 * N2 + ab;
   n[0] = (T)nf[0];
   n[1] = (T)nf[N2];
   n[2] = (T)nf[2 * N2];
+}
+
+// Outside state at face point ab: the neighbour's stored trace
+// (orientation-mapped), the caller's trace on import faces, the ghost state
+// on Dirichlet faces; nothing on walls (their state is built from the own one).
+template <int N, typename T>
+__device__ __forceinline__ void load_outside_state(const Run<T>& R, int ab, int32_t code, T q[9]) {
+  constexpr int N2 = N * N;
   if (code >= 0) {
     const int64_t en = code >> 6;
     const int fn = (code >> 3) & 7, o = code & 7;
@@ -314,6 +358,12 @@ __device__ __forceinline__ void load_outside(const Run<T>& R, int f, int ab, int
       for (int v = 0; v < 9; ++v) q[v] = T(0);
     }
   }
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void load_outside(const Run<T>& R, int f, int ab, int32_t code, T q[9], T n[3]) {
+  load_normal<N>(R, f, ab, n);
+  load_outside_state<N>(R, ab, code, q);
 }
 
 // ---------------------------------------------------------------------------
@@ -385,7 +435,8 @@ void k_volume(Launch L) {
   constexpr int UN = (9 * NI > 9 * 6 * N2) ? 9 * NI : 9 * 6 * N2;
   // a thread keeps its own face point / interior flux points across phases
   // when one pass covers them all
-  constexpr bool FACE_REG = 6 * N2 <= BS;
+  constexpr int FL = face_lanes<N>();
+  constexpr bool FACE_REG = FL <= BS;
   constexpr bool INT_REG = NI <= BS;
   // the element's point rows (Q, then grad_x Q); FP64 rows have two spare
   // slots, where the basis tables live (I in slot 36, D in slot 37)
@@ -395,10 +446,14 @@ void k_volume(Launch L) {
   __shared__ __align__(16) T sR[N3 * RS];
   __shared__ T sU[UN];  // face jumps (common value - own trace), then fluxes: 9 per point
   __shared__ double sRed[BS / 64][10];
-  __shared__ T sIa[PADTAB ? 1 : (N + 1) * N], sDa[PADTAB ? 1 : N * (N + 1)];
+  // DI (the derivative of the SP polynomial at the SPs) follows I in slot 36
+  // where the rows leave room
+  constexpr bool DIPAD = PADTAB && (N + 1) * N + N * N <= N3;
+  __shared__ T sIa[PADTAB ? 1 : (N + 1) * N], sDa[PADTAB ? 1 : N * (N + 1)], sDIa[DIPAD ? 1 : N * N];
   T* const sI = PADTAB ? sR + 36 : sIa;
   T* const sD = PADTAB ? sR + 37 : sDa;
-  constexpr int is = PADTAB ? RS : 1, ds = PADTAB ? RS : 1;
+  T* const sDI = DIPAD ? sR + 36 + (N + 1) * N * RS : sDIa;
+  constexpr int is = PADTAB ? RS : 1, ds = PADTAB ? RS : 1, dis = DIPAD ? RS : 1;
   // the physical parameters, read from LDS where they are used: held in
   // scalar registers for the whole element they overflow them
   __shared__ Phys<T> sP;
@@ -421,14 +476,26 @@ void k_volume(Launch L) {
     const GBL int32_t* nb6 = R.nbr + e * 6;
     const bool use_kr = R.P.kr_scale != T(0);
 
-    // A. every global read of this element is issued here: the state into
-    //    LDS; the chain-rule factors and position of this thread's SP; the
-    //    outside state and normal of this thread's face point; the metric at
-    //    this thread's interior flux points of the three families.
-    for (int i = tid; i < 9 * N3; i += BS) sR[(i % N3) * RS + i / N3] = (T)Qe[i];
+    // A. every global read of this element is issued before any of them is
+    //    used (one round trip, plus one for the neighbour gather that needs
+    //    the face's neighbour code): the state, the chain-rule factors and
+    //    position of this thread's SP, the normal and outside state of this
+    //    thread's face point, the metric at this thread's interior flux points
+    //    of the three families, and the basis tables; then the LDS writes.
+    int32_t fcode = 0;
+    int lf = 0, lab = 0;  // this lane's face point (face passes)
+    const bool has_face = FACE_REG && face_lane<N>(tid, lf, lab);
+    if (has_face) fcode = nb6[lf];
+    constexpr int QK = (9 * N3 + BS - 1) / BS;  // state values per thread
+    T qv[QK];
+#pragma unroll
+    for (int k = 0; k < QK; ++k) {
+      const int i = tid + k * BS;
+      qv[k] = i < 9 * N3 ? (T)Qe[i] : T(0);
+    }
     T ji = T(0), Sj[3][3], xs[3] = {T(0), T(0), T(0)};
     if (tid < N3) {
-      ji = recip((T)R.detJ[e * N3 + tid]);
+      ji = (T)R.detJ[e * N3 + tid];
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -437,12 +504,7 @@ void k_volume(Launch L) {
       for (int c = 0; c < 3; ++c) xs[c] = (T)R.x_sp[(e * 3 + c) * N3 + tid];
     }
     T fq[9], fn[3];  // face point: outside state (neighbour trace or ghost), normal
-    int32_t fcode = 0;
-    if (FACE_REG && tid < 6 * N2) {
-      const int f = tid / N2, ab = tid % N2;
-      fcode = nb6[f];
-      load_outside<N>(R, f, ab, fcode, fq, fn);
-    }
+    if (has_face) load_normal<N>(R, lf, lab, fn);
     T Sint[3][3];  // metric at the interior flux point `tid` of each family
     if (!DIAG && INT_REG && tid < NI) {
       const int line = tid / (N - 1), f = 1 + tid % (N - 1);
@@ -453,15 +515,33 @@ void k_volume(Launch L) {
         for (int c = 0; c < 3; ++c) Sint[d][c] = (T)Se[(d * 3 + c) * NF + fi];
       }
     }
-    stage_tables<N>(sI, sD, is, ds);  // after the element's loads are in flight
+    T tI = T(0), tD = T(0), tDI = T(0);
+    if (tid < (N + 1) * N) {
+      tI = tb.I[tid / N][tid % N];
+      tD = tb.D[tid / (N + 1)][tid % (N + 1)];
+    }
+    if (tid < N * N) tDI = tb.DI[tid / N][tid % N];
+    if (has_face) load_outside_state<N>(R, lab, fcode, fq);
+#pragma unroll
+    for (int k = 0; k < QK; ++k) {
+      const int i = tid + k * BS;
+      if (i < 9 * N3) sR[(i % N3) * RS + i / N3] = qv[k];
+    }
+    if (tid < (N + 1) * N) {
+      sI[tid * is] = tI;
+      sD[tid * ds] = tD;
+    }
+    if (tid < N * N) sDI[tid * dis] = tDI;
+    if (tid < N3) ji = recip(ji);
     __syncthreads();
 
     // B. BR1 common solution at the 6 N^2 face points (one per thread): the
     //    own trace, and the common value from the outside (neighbour, wall or
     //    ghost) state, stored as the jump (common value - own trace) that
     //    the gradient correction uses.
-    for (int it = tid; it < 6 * N2; it += BS) {
-      const int f = it / N2, ab = it % N2;
+    for (int it = tid; it < FL; it += BS) {
+      int f, ab;
+      if (!face_lane<N>(it, f, ab)) continue;
       T q_out[9], n[3];
       int32_t code;
       if (FACE_REG) {
@@ -488,7 +568,7 @@ void k_volume(Launch L) {
 #pragma unroll
         for (int v = 0; v < 9; ++v) own[v] += wi * row[v];
       }
-      T* dst = sU + it * 9;
+      T* dst = sU + (f * N2 + ab) * 9;
       const int g = code >= 0 ? -1 : ((-code - 1) & 3);
       if (code >= 0 || g >= 2 || wsel(g, P.wall_kind) == 1) {
 #pragma unroll
@@ -509,26 +589,48 @@ void k_volume(Launch L) {
     // C. gradient at the solution points.
     //    C1: derivative of each variable along each line: the solution
     //    polynomial's own derivative plus the lifting of the two end jumps;
-    //    one (direction, line, variable) per thread, point index uniform so
-    //    the table entries are scalar loads.  Written to the gradient slots
-    //    of the point rows as dQ/dxi_d.
-    for (int it = tid; it < 3 * 9 * N2; it += BS) {
-      const int v = it % 9, t = it / 9, pq = t % N2, d = t / N2;  // variable fastest
-      const int st = d == 0 ? 1 : (d == 1 ? N : N2);
-      const int s0 = sp_line<N>(d, pq % N, pq / N, 0);
-      T ln[N];
+    //    one (direction, line, variable) per thread.  The N x (N + 2) table
+    //    entries (DI, and the end columns of D) are read from LDS into
+    //    registers once, where they fit.  Written to the gradient slots of
+    //    the point rows as dQ/dxi_d.
+    {
+      constexpr bool CREG = N * (N + 2) * (int)sizeof(T) <= 384;
+      T cD[CREG ? N : 1][N + 2];
+      if constexpr (CREG) {
 #pragma unroll
-      for (int j = 0; j < N; ++j) ln[j] = sR[(s0 + j * st) * RS + v];
-      const T j0 = sU[((2 * d) * N2 + pq) * 9 + v], jN = sU[((2 * d + 1) * N2 + pq) * 9 + v];
-      T* out = sR + 9 + v * 3 + d;
-      // one row of the tables per step (scalar loads), not all N^2 + 2N
-      // entries held in scalar registers at once
+        for (int i = 0; i < N; ++i) {
+#pragma unroll
+          for (int j = 0; j < N; ++j) cD[i][j] = sDI[(i * N + j) * dis];
+          cD[i][N] = sD[(i * NP) * ds];
+          cD[i][N + 1] = sD[(i * NP + N) * ds];
+        }
+      }
+      for (int it = tid; it < 3 * 9 * N2; it += BS) {
+        const int v = it % 9, t = it / 9, pq = t % N2, d = t / N2;  // variable fastest
+        const int st = d == 0 ? 1 : (d == 1 ? N : N2);
+        const int s0 = sp_line<N>(d, pq % N, pq / N, 0);
+        T ln[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) ln[j] = sR[(s0 + j * st) * RS + v];
+        const T j0 = sU[((2 * d) * N2 + pq) * 9 + v], jN = sU[((2 * d + 1) * N2 + pq) * 9 + v];
+        T* out = sR + 9 + v * 3 + d;
+        if constexpr (CREG) {
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+            T dd = cD[i][N] * j0 + cD[i][N + 1] * jN;
+#pragma unroll
+            for (int j = 0; j < N; ++j) dd += cD[i][j] * ln[j];
+            out[(s0 + i * st) * RS] = dd;
+          }
+        } else {
 #pragma unroll 1
-      for (int i = 0; i < N; ++i) {
-        T dd = tb.D[i][0] * j0 + tb.D[i][N] * jN;
+          for (int i = 0; i < N; ++i) {
+            T dd = sD[(i * NP) * ds] * j0 + sD[(i * NP + N) * ds] * jN;
 #pragma unroll
-        for (int j = 0; j < N; ++j) dd += tb.DI[i][j] * ln[j];
-        out[(s0 + i * st) * RS] = dd;
+            for (int j = 0; j < N; ++j) dd += sDI[(i * N + j) * dis] * ln[j];
+            out[(s0 + i * st) * RS] = dd;
+          }
+        }
       }
     }
     __syncthreads();
@@ -599,8 +701,10 @@ void k_volume(Launch L) {
 #pragma unroll
     for (int v = 0; v < 9; ++v) div[v] = T(0);
 #pragma unroll 1
-    for (int it = tid; it < 6 * N2; it += BS) {
-      const int face = it / N2, ab = it % N2, p = ab % N, q = ab / N;
+    for (int it = tid; it < FL; it += BS) {
+      int face, ab;
+      if (!face_lane<N>(it, face, ab)) continue;
+      const int p = ab % N, q = ab / N;
       const int d = face >> 1, fe = (face & 1) ? N : 0;
       const int st = d == 0 ? 1 : (d == 1 ? N : N2);
       const int s0 = sp_line<N>(d, p, q, 0);
@@ -659,7 +763,7 @@ void k_volume(Launch L) {
       // the flux polynomial of family d takes -F at its coordinate 0, +F at 1
       const T sg = (face & 1) ? T(1) : T(-1);
 #pragma unroll
-      for (int v = 0; v < 9; ++v) sU[it * 9 + v] = sg * F[v];
+      for (int v = 0; v < 9; ++v) sU[(face * N2 + ab) * 9 + v] = sg * F[v];
     }
     __syncthreads();
     if (tid < N3) {
