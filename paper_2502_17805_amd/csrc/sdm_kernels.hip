@@ -589,12 +589,15 @@ void k_volume(Launch L) {
     // C. gradient at the solution points.
     //    C1: derivative of each variable along each line: the solution
     //    polynomial's own derivative plus the lifting of the two end jumps;
-    //    one (direction, line, variable) per thread.  The N x (N + 2) table
+    //    one (direction, line, variable) per item.  The N x (N + 2) table
     //    entries (DI, and the end columns of D) are read from LDS into
-    //    registers once, where they fit.  Written to the gradient slots of
-    //    the point rows as dQ/dxi_d.
+    //    registers once, where they fit; a thread then takes two items per
+    //    step, both items' LDS reads issued before either's arithmetic.
+    //    Written to the gradient slots of the point rows as dQ/dxi_d.
     {
+      constexpr int NIT = 3 * 9 * N2;
       constexpr bool CREG = N * (N + 2) * (int)sizeof(T) <= 384;
+      constexpr int K = CREG ? 2 : 1;
       T cD[CREG ? N : 1][N + 2];
       if constexpr (CREG) {
 #pragma unroll
@@ -605,30 +608,52 @@ void k_volume(Launch L) {
           cD[i][N + 1] = sD[(i * NP + N) * ds];
         }
       }
-      for (int it = tid; it < 3 * 9 * N2; it += BS) {
-        const int v = it % 9, t = it / 9, pq = t % N2, d = t / N2;  // variable fastest
-        const int st = d == 0 ? 1 : (d == 1 ? N : N2);
-        const int s0 = sp_line<N>(d, pq % N, pq / N, 0);
-        T ln[N];
+      for (int it0 = tid; it0 < NIT; it0 += K * BS) {
+        T ln[K][N], j0[K], jN[K];
+        int s0[K], st[K], v[K], d[K];
+        bool on[K];
 #pragma unroll
-        for (int j = 0; j < N; ++j) ln[j] = sR[(s0 + j * st) * RS + v];
-        const T j0 = sU[((2 * d) * N2 + pq) * 9 + v], jN = sU[((2 * d + 1) * N2 + pq) * 9 + v];
-        T* out = sR + 9 + v * 3 + d;
+        for (int u = 0; u < K; ++u) {
+          // an item past the end repeats item it0 (read only, not stored)
+          const int it = it0 + u * BS;
+          on[u] = it < NIT;
+          const int itc = on[u] ? it : it0;
+          v[u] = itc % 9;  // variable fastest
+          const int t = itc / 9, pq = t % N2;
+          d[u] = t / N2;
+          st[u] = d[u] == 0 ? 1 : (d[u] == 1 ? N : N2);
+          s0[u] = sp_line<N>(d[u], pq % N, pq / N, 0);
+#pragma unroll
+          for (int j = 0; j < N; ++j) ln[u][j] = sR[(s0[u] + j * st[u]) * RS + v[u]];
+          j0[u] = sU[((2 * d[u]) * N2 + pq) * 9 + v[u]];
+          jN[u] = sU[((2 * d[u] + 1) * N2 + pq) * 9 + v[u]];
+        }
         if constexpr (CREG) {
+          T dd[K][N];
 #pragma unroll
-          for (int i = 0; i < N; ++i) {
-            T dd = cD[i][N] * j0 + cD[i][N + 1] * jN;
+          for (int u = 0; u < K; ++u)
 #pragma unroll
-            for (int j = 0; j < N; ++j) dd += cD[i][j] * ln[j];
-            out[(s0 + i * st) * RS] = dd;
-          }
+            for (int i = 0; i < N; ++i) {
+              T x = cD[i][N] * j0[u] + cD[i][N + 1] * jN[u];
+#pragma unroll
+              for (int j = 0; j < N; ++j) x += cD[i][j] * ln[u][j];
+              dd[u][i] = x;
+            }
+#pragma unroll
+          for (int u = 0; u < K; ++u)
+            if (on[u]) {
+              T* out = sR + 9 + v[u] * 3 + d[u];
+#pragma unroll
+              for (int i = 0; i < N; ++i) out[(s0[u] + i * st[u]) * RS] = dd[u][i];
+            }
         } else {
+          T* out = sR + 9 + v[0] * 3 + d[0];
 #pragma unroll 1
           for (int i = 0; i < N; ++i) {
-            T dd = sD[(i * NP) * ds] * j0 + sD[(i * NP + N) * ds] * jN;
+            T x = sD[(i * NP) * ds] * j0[0] + sD[(i * NP + N) * ds] * jN[0];
 #pragma unroll
-            for (int j = 0; j < N; ++j) dd += sDI[(i * N + j) * dis] * ln[j];
-            out[(s0 + i * st) * RS] = dd;
+            for (int j = 0; j < N; ++j) x += sDI[(i * N + j) * dis] * ln[0][j];
+            out[(s0[0] + i * st[0]) * RS] = x;
           }
         }
       }
