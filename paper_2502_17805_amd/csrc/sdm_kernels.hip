@@ -261,8 +261,9 @@ __device__ __forceinline__ bool face_lane(int t, int& face, int& ab) {
 // k_volume keeps Q and grad_x Q of its element in LDS point by point: row sp
 // of `RS` values holds Q (0..8), then the gradient (9 + 3 v + c: component c
 // of variable v), then padding; a point's 36 fields are contiguous, so one
-// 16-byte LDS read fetches two of them.  RS = 38 doubles (row 304 B: rows of
-// 8 consecutive points fall in distinct banks) or 36 floats.
+// 16-byte LDS read fetches two of them.  RS = 38 doubles (a row is 19
+// 16-byte units, so 16 consecutive rows start in 16 distinct bank groups)
+// or 36 floats.
 template <typename T>
 constexpr int row_stride() {
   return sizeof(T) == 8 ? 38 : 36;
@@ -273,46 +274,65 @@ constexpr int row_stride() {
 // interpolation weights; optionally the radiative diffusivity sampled at
 // the SPs and interpolated the same way.
 template <int N, typename T>
+__device__ __forceinline__ void load_row(const T* sR, int sidx, T a[36]) {
+  constexpr int RS = row_stride<T>();
+  if constexpr (sizeof(T) == 8) {
+    const double2* row = reinterpret_cast<const double2*>(sR + sidx * RS);
+#pragma unroll
+    for (int j = 0; j < 18; ++j) {
+      const double2 x = row[j];
+      a[2 * j] = x.x;
+      a[2 * j + 1] = x.y;
+    }
+  } else {
+    const float4* row = reinterpret_cast<const float4*>(sR + sidx * RS);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      const float4 x = row[j];
+      a[4 * j] = x.x;
+      a[4 * j + 1] = x.y;
+      a[4 * j + 2] = x.z;
+      a[4 * j + 3] = x.w;
+    }
+  }
+}
+
+// Q and grad_x Q at one flux point from the point rows: one pass over the
+// line's N solution points accumulating all 36 fields (the first point's
+// products start the sums); w[i * ws] are the interpolation weights;
+// optionally the radiative diffusivity sampled at the SPs and interpolated
+// the same way.
+template <int N, typename T>
 __device__ __forceinline__ T interp_rows(const T* sR, const T* w, int ws, int s0, int st, T qf[9], T gf[27],
                                          bool use_kr, const Run<T>& R) {
-  constexpr int N3 = N * N * N, RS = row_stride<T>();
-#pragma unroll
-  for (int v = 0; v < 9; ++v) qf[v] = T(0);
-#pragma unroll
-  for (int k = 0; k < 27; ++k) gf[k] = T(0);
+  constexpr int N3 = N * N * N;
   T kf = T(0);
+  {
+    const T w0 = w[0];
+    T a[36];
+    load_row<N>(sR, s0, a);
+#pragma unroll
+    for (int v = 0; v < 9; ++v) qf[v] = w0 * a[v];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) gf[k] = w0 * a[9 + k];
+  }
 #pragma unroll 1
-  for (int i = 0; i < N; ++i) {
+  for (int i = 1; i < N; ++i) {
     const T wi = w[i * ws];
-    const int sidx = s0 + i * st;
     T a[36];  // the row's 36 fields, 16 bytes per LDS read
-    if constexpr (sizeof(T) == 8) {
-      const double2* row = reinterpret_cast<const double2*>(sR + sidx * RS);
-#pragma unroll
-      for (int j = 0; j < 18; ++j) {
-        const double2 x = row[j];
-        a[2 * j] = x.x;
-        a[2 * j + 1] = x.y;
-      }
-    } else {
-      const float4* row = reinterpret_cast<const float4*>(sR + sidx * RS);
-#pragma unroll
-      for (int j = 0; j < 9; ++j) {
-        const float4 x = row[j];
-        a[4 * j] = x.x;
-        a[4 * j + 1] = x.y;
-        a[4 * j + 2] = x.z;
-        a[4 * j + 3] = x.w;
-      }
-    }
+    load_row<N>(sR, s0 + i * st, a);
 #pragma unroll
     for (int v = 0; v < 9; ++v) qf[v] += wi * a[v];
 #pragma unroll
     for (int k = 0; k < 27; ++k) gf[k] += wi * a[9 + k];
-    if (use_kr) {
+  }
+  if (use_kr) {
+#pragma unroll 1
+    for (int i = 0; i < N; ++i) {
+      const int sidx = s0 + i * st;
       const T x[3] = {(T)R.x_sp[(R.e * 3 + 0) * N3 + sidx], (T)R.x_sp[(R.e * 3 + 1) * N3 + sidx],
                       (T)R.x_sp[(R.e * 3 + 2) * N3 + sidx]};
-      kf += wi * kappa_r(x, R.P);
+      kf += w[i * ws] * kappa_r(x, R.P);
     }
   }
   return kf;
@@ -478,20 +498,18 @@ void k_volume(Launch L) {
 
     // A. every global read of this element is issued before any of them is
     //    used (one round trip, plus one for the neighbour gather that needs
-    //    the face's neighbour code): the state, the chain-rule factors and
-    //    position of this thread's SP, the normal and outside state of this
+    //    the face's neighbour code): the state and the chain-rule factors and
+    //    position of this thread's SP (its state goes to its point row), the normal and outside state of this
     //    thread's face point, the metric at this thread's interior flux points
     //    of the three families, and the basis tables; then the LDS writes.
     int32_t fcode = 0;
     int lf = 0, lab = 0;  // this lane's face point (face passes)
     const bool has_face = FACE_REG && face_lane<N>(tid, lf, lab);
     if (has_face) fcode = nb6[lf];
-    constexpr int QK = (9 * N3 + BS - 1) / BS;  // state values per thread
-    T qv[QK];
+    T qv[9];
+    if (tid < N3) {
 #pragma unroll
-    for (int k = 0; k < QK; ++k) {
-      const int i = tid + k * BS;
-      qv[k] = i < 9 * N3 ? (T)Qe[i] : T(0);
+      for (int v = 0; v < 9; ++v) qv[v] = (T)Qe[v * N3 + tid];
     }
     T ji = T(0), Sj[3][3], xs[3] = {T(0), T(0), T(0)};
     if (tid < N3) {
@@ -522,10 +540,9 @@ void k_volume(Launch L) {
     }
     if (tid < N * N) tDI = tb.DI[tid / N][tid % N];
     if (has_face) load_outside_state<N>(R, lab, fcode, fq);
+    if (tid < N3) {
 #pragma unroll
-    for (int k = 0; k < QK; ++k) {
-      const int i = tid + k * BS;
-      if (i < 9 * N3) sR[(i % N3) * RS + i / N3] = qv[k];
+      for (int v = 0; v < 9; ++v) sR[tid * RS + v] = qv[v];
     }
     if (tid < (N + 1) * N) {
       sI[tid * is] = tI;
@@ -560,9 +577,9 @@ void k_volume(Launch L) {
       const T* wI = sI + ((f & 1) ? N : 0) * N * is;
       T own[9];
 #pragma unroll
-      for (int v = 0; v < 9; ++v) own[v] = T(0);
+      for (int v = 0; v < 9; ++v) own[v] = wI[0] * sR[s0 * RS + v];
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
+      for (int i = 1; i < N; ++i) {
         const T wi = wI[i * is];
         const T* row = sR + (s0 + i * st) * RS;
 #pragma unroll
