@@ -156,6 +156,24 @@ def run_shard(sd, mesh, Q, pr, dt, steps, warmup):
             "value": dof * 5 / (ms * 1e-3), "unit": "DOF*RK-stage updates/s"}
 
 
+def copy_rate(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (GB/s, bytes read + written) of a plain
+    1 GiB copy: the practical HBM streaming rate the stage is compared to."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del a, b
+    return 2 * nbytes * reps / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(cfg, Q_fn, pr, dt):
     from oracle import oracle as o
     Nz, Nr, p, _, _ = cfg
@@ -260,6 +278,16 @@ def main():
     stage_roof = {"alg_bytes": alg_bytes("stage", N, mesh.E), "ms": t_stage * 1e3,
                   "hbm_frac": alg_bytes("stage", N, mesh.E) / t_stage / 1e9 / HBM_PEAK_GBS,
                   "fp64_frac": alg_flops(N) * mesh.E / t_stage / 1e12 / FP64_PEAK_TFLOPS}
+    # measured HBM bytes of a stage (volume + finish pass, rocprofv3 counters
+    # taken on the current kernel source), against the spec peak and against
+    # the copy rate measured here
+    tv, tf = measured_traffic("volume", args.config, 0), measured_traffic("finish_stage", args.config, 0)
+    crate = copy_rate(torch)
+    stage_roof["copy_gbs"] = crate
+    if tv and tf:
+        stage_roof.update({"measured_bytes": tv + tf,
+                           "measured_hbm_frac": (tv + tf) / t_stage / 1e9 / HBM_PEAK_GBS,
+                           "measured_copy_frac": (tv + tf) / t_stage / 1e9 / crate})
     out = {
         "metric": "SD-MHD DOF*RK-stage updates/s (FP64)",
         "value": value,
@@ -279,6 +307,8 @@ def main():
         "roofline": roof,
         "stage_roofline": stage_roof,
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "variable_dof_value": 9 * value,
+        "variable_dof_unit": "variable-DOF*RK-stage updates/s (9 variables per solution point)",
     }
     if 1 in res:
         ms1, _, prof1, d1 = res[1]

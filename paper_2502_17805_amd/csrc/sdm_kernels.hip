@@ -431,6 +431,22 @@ __global__ __launch_bounds__(block_threads<N>()) void k_traces(Launch L) {
   }
 }
 
+// divergence contribution of the interior flux points of family d (stored
+// in sU, 9 values per point, line-major) at the SP (ia0, ia1, ia2)
+template <int N, typename T>
+__device__ __forceinline__ void lift_family(int d, int ia0, int ia1, int ia2, const T* sD, int ds, const T* sU,
+                                            T div[9]) {
+  constexpr int NP = N + 1;
+  const int p = d == 0 ? ia1 : ia0, q = d == 2 ? ia1 : ia2, i = d == 0 ? ia0 : (d == 1 ? ia1 : ia2);
+  const int base = (p + N * q) * (N - 1);
+#pragma unroll 1
+  for (int f = 1; f < N; ++f) {
+    const T df = sD[(i * NP + f) * ds];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) div[v] += df * sU[(base + f - 1) * 9 + v];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // k_volume
 // ---------------------------------------------------------------------------
@@ -736,9 +752,11 @@ void k_volume(Launch L) {
     }
 
     // D. fluxes and their divergence.
-    //    D1: the 6 N^2 face points (common fluxes); D2: their lifting into the
-    //    divergence; then per family d: D3 the interior flux points and D4
-    //    their contribution to the divergence.  sU is reused by each pass.
+    //    D1: the 6 N^2 face points (common fluxes) into sU; then per family
+    //    d the interior flux points (one per thread, held in registers) while
+    //    the SP threads lift the previous pass's fluxes (the faces' before
+    //    family 0) into the divergence; then the family's fluxes replace
+    //    them in sU.  The last family is lifted after the loop.
     T div[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v) div[v] = T(0);
@@ -808,59 +826,52 @@ void k_volume(Launch L) {
       for (int v = 0; v < 9; ++v) sU[(face * N2 + ab) * 9 + v] = sg * F[v];
     }
     __syncthreads();
-    if (tid < N3) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int p = d == 0 ? ia1 : ia0, q = d == 2 ? ia1 : ia2, i = d == 0 ? ia0 : (d == 1 ? ia1 : ia2);
-        const int pq = p + N * q;
-        const T d0 = sD[(i * NP) * ds], dN = sD[(i * NP + N) * ds];
-#pragma unroll
-        for (int v = 0; v < 9; ++v)
-          div[v] += d0 * sU[((2 * d) * N2 + pq) * 9 + v] + dN * sU[((2 * d + 1) * N2 + pq) * 9 + v];
-      }
-    }
-    __syncthreads();
+    static_assert(INT_REG, "one interior flux point per thread");
+    // per family d: the interior fluxes into registers while the SP threads
+    // lift the fluxes of the previous pass (the faces before family 0), then
+    // the fluxes go to sU once every thread has read the previous ones
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const int st = d == 0 ? 1 : (d == 1 ? N : N2);
-#pragma unroll 1
-      for (int it = tid; it < NI; it += BS) {
-        const int line = it / (N - 1), f = 1 + it % (N - 1);
+      T F[9];
+      if (tid < NI) {
+        const int st = d == 0 ? 1 : (d == 1 ? N : N2);
+        const int line = tid / (N - 1), f = 1 + tid % (N - 1);
         const int p = line % N, q = line / N;
         const int s0 = sp_line<N>(d, p, q, 0);
         T qf[9], gf[27];
         T kf = interp_rows<N>(sR, sI + f * N * is, is, s0, st, qf, gf, use_kr, R);
-        T Sd[3];
-        if (INT_REG) {
-          Sd[0] = Sint[d][0]; Sd[1] = Sint[d][1]; Sd[2] = Sint[d][2];
-        } else {
-          const int fi = fp_fam<N>(d, f, p, q);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) Sd[c] = (T)Se[(d * 3 + c) * NF + fi];
-        }
+        const T Sd[3] = {Sint[d][0], Sint[d][1], Sint[d][2]};
         ViscLocal<T> vl;
         viscous_local(qf, gf, kf, P, vl);
-        T Fv[7], F[9];
+        T Fv[7];
         flux_viscous7(vl, Sd, P, Fv);
         flux_inviscid(qf, Sd, P, F);
 #pragma unroll
         for (int c = 0; c < 7; ++c) F[1 + c] -= Fv[c];
-#pragma unroll
-        for (int v = 0; v < 9; ++v) sU[it * 9 + v] = F[v];
       }
-      __syncthreads();
       if (tid < N3) {
-        const int p = d == 0 ? ia1 : ia0, q = d == 2 ? ia1 : ia2, i = d == 0 ? ia0 : (d == 1 ? ia1 : ia2);
-        const int base = (p + N * q) * (N - 1);
-#pragma unroll 1
-        for (int f = 1; f < N; ++f) {
-          const T df = sD[(i * NP + f) * ds];
+        if (d == 0) {
 #pragma unroll
-          for (int v = 0; v < 9; ++v) div[v] += df * sU[(base + f - 1) * 9 + v];
+          for (int e2 = 0; e2 < 3; ++e2) {
+            const int p = e2 == 0 ? ia1 : ia0, q = e2 == 2 ? ia1 : ia2, i = e2 == 0 ? ia0 : (e2 == 1 ? ia1 : ia2);
+            const int pq = p + N * q;
+            const T d0 = sD[(i * NP) * ds], dN = sD[(i * NP + N) * ds];
+#pragma unroll
+            for (int v = 0; v < 9; ++v)
+              div[v] += d0 * sU[((2 * e2) * N2 + pq) * 9 + v] + dN * sU[((2 * e2 + 1) * N2 + pq) * 9 + v];
+          }
+        } else {
+          lift_family<N>(d - 1, ia0, ia1, ia2, sD, ds, sU, div);
         }
       }
       __syncthreads();
+      if (tid < NI) {
+#pragma unroll
+        for (int v = 0; v < 9; ++v) sU[tid * 9 + v] = F[v];
+      }
+      __syncthreads();
     }
+    if (tid < N3) lift_family<N>(2, ia0, ia1, ia2, sD, ds, sU, div);
 
     // E. sources (Eq. "M") and the partial residual -div/|J| + M
     if (tid < N3) {
