@@ -86,6 +86,8 @@ def lib():
         L.or_ssprk53_table.argtypes = [vp, vp, vp]
         L.or_diagnostics.argtypes = [vp, C.POINTER(Params), vp, vp, vp]
         L.or_diagnostics.restype = ip
+        L.or_sph_profiles.argtypes = [vp, vp, C.c_double, C.c_double, ip, ip, vp]
+        L.or_sph_profiles.restype = ip
         L.or_tables.argtypes = [ip, vp, vp, vp, vp, vp]
         L.or_tables.restype = ip
         L.or_threads.restype = ip
@@ -210,6 +212,15 @@ class Mesh:
         if lib().or_ssprk53_step(self._h, C.byref(prm), _ptr(Q), _ptr(g), float(dt)):
             raise RuntimeError("oracle step failed")
         return Q
+
+    def sph_profiles(self, Q, n_r, n_th, rb=0.70, rt=0.98):
+        """Per (r, theta) bin: sums of w, w V_phi, w V_mer, w (B_r^2 + B_theta^2)/2,
+        w B_phi^2/2 over the SPs in the bin, shape (n_r, n_th, 5)."""
+        Q = np.ascontiguousarray(Q, dtype=np.float64)
+        out = np.zeros((n_r, n_th, 5))
+        if lib().or_sph_profiles(self._h, _ptr(Q), float(rb), float(rt), int(n_r), int(n_th), _ptr(out)):
+            raise ValueError("bad bin counts or radii")
+        return out
 
     def diagnostics(self, prm, Q, ghost=None):
         Q = np.ascontiguousarray(Q, dtype=np.float64)

@@ -1276,6 +1276,79 @@ int or_diagnostics(const or_mesh* m, const or_params* P, const double* Q, const 
   return 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* Spherical components (Sec. Results)                                  */
+/* ------------------------------------------------------------------ */
+
+/* The paper reports the differential rotation as the longitude (and time)
+ * average of V_phi, the meridional flow as that of V_mer = sqrt(V_r^2 +
+ * V_theta^2), and the magnetic energy split into poloidal (B_r^2 + B_theta^2)
+ * and toroidal (B_phi^2) parts.  Readings: rationalized units (the
+ * factor 1/(8 pi) becomes 1/2, as for E_B); the longitude average over a
+ * bin of uniform (r, theta) bins, r in [rb, rt], theta in [0, pi], is the
+ * volume-weighted mean of the SPs the bin holds; a bin holds SP x when
+ * floor((|x| - rb) / (rt - rb) * n_r) and floor(theta / pi * n_th) (clamped
+ * to the range) are its indices, theta = atan2(sqrt(x^2 + y^2), z).  On the
+ * polar axis (x = y = 0) phi_hat = (0, 1, 0) and theta_hat = (1, 0, 0) sign z.
+ * out[(ir * n_th + it) * 5 + k]: k = 0 sum of w, 1 sum of w V_phi, 2 sum of
+ * w V_mer, 3 sum of w (B_r^2 + B_theta^2)/2, 4 sum of w B_phi^2/2, with w =
+ * W_a W_b W_c |J| at the SP. */
+static void sph_basis(const double x[3], double rh[3], double th[3], double ph[3], double* r,
+                      double* theta) {
+  const double rc = sqrt(x[0] * x[0] + x[1] * x[1]);
+  *r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+  *theta = atan2(rc, x[2]);
+  for (int c = 0; c < 3; ++c) rh[c] = x[c] / *r;
+  if (rc > 0.0) {
+    ph[0] = -x[1] / rc; ph[1] = x[0] / rc; ph[2] = 0.0;
+    /* theta_hat = phi_hat x r_hat */
+    th[0] = ph[1] * rh[2] - ph[2] * rh[1];
+    th[1] = ph[2] * rh[0] - ph[0] * rh[2];
+    th[2] = ph[0] * rh[1] - ph[1] * rh[0];
+  } else {
+    ph[0] = 0.0; ph[1] = 1.0; ph[2] = 0.0;
+    th[0] = x[2] >= 0.0 ? 1.0 : -1.0; th[1] = 0.0; th[2] = 0.0;
+  }
+}
+
+int or_sph_profiles(const or_mesh* m, const double* Q, double rb, double rt, int n_r, int n_th,
+                    double* out) {
+  if (n_r < 1 || n_th < 1 || !(rt > rb)) return -1;
+  const int N = m->N, N3 = N * N * N;
+  const double pi = 3.14159265358979323846;
+  for (int64_t i = 0; i < (int64_t)n_r * n_th * 5; ++i) out[i] = 0.0;
+  for (int64_t e = 0; e < m->E; ++e)
+    for (int c = 0; c < N; ++c)
+      for (int b = 0; b < N; ++b)
+        for (int a = 0; a < N; ++a) {
+          const int q = SP(N, a, b, c);
+          const double w = m->t.W[a] * m->t.W[b] * m->t.W[c] * m->detJ[e * N3 + q];
+          const double x[3] = {m->xsp[(e * 3 + 0) * N3 + q], m->xsp[(e * 3 + 1) * N3 + q],
+                               m->xsp[(e * 3 + 2) * N3 + q]};
+          double rh[3], th[3], ph[3], r, theta;
+          sph_basis(x, rh, th, ph, &r, &theta);
+          int ir = (int)floor((r - rb) / (rt - rb) * n_r);
+          int it = (int)floor(theta / pi * n_th);
+          ir = ir < 0 ? 0 : (ir >= n_r ? n_r - 1 : ir);
+          it = it < 0 ? 0 : (it >= n_th ? n_th - 1 : it);
+          const double* s = &Q[e * NV * N3 + q];
+          const double u[3] = {s[N3] / s[0], s[2 * N3] / s[0], s[3 * N3] / s[0]};
+          const double B[3] = {s[5 * N3], s[6 * N3], s[7 * N3]};
+          double ur = 0, ut = 0, up = 0, br = 0, bt = 0, bp = 0;
+          for (int k = 0; k < 3; ++k) {
+            ur += u[k] * rh[k]; ut += u[k] * th[k]; up += u[k] * ph[k];
+            br += B[k] * rh[k]; bt += B[k] * th[k]; bp += B[k] * ph[k];
+          }
+          double* o = &out[((int64_t)ir * n_th + it) * 5];
+          o[0] += w;
+          o[1] += w * up;
+          o[2] += w * sqrt(ur * ur + ut * ut);
+          o[3] += w * 0.5 * (br * br + bt * bt);
+          o[4] += w * 0.5 * bp * bp;
+        }
+  return 0;
+}
+
 int or_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

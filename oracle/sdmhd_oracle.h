@@ -33,6 +33,10 @@
  *                       convergence, table = independent derivation
  *   or_diagnostics      exact integrals of uniform and polynomial states,
  *                       div B of a linear field, NaN flag
+ *   or_sph_profiles     poloidal + toroidal = E_B of or_diagnostics, purely
+ *                       toroidal / radial / dipole fields, constant radial,
+ *                       polar and azimuthal flows, bin volumes = shell
+ *                       volumes of the bins
  * Parity unpinned beyond invariants: the wall treatments (mirror and common
  * states, stress-free and magnetic wall fluxes) are pinned only by zero
  * mass flux, zero tangential stress, zero energy flux through a conducting
@@ -121,6 +125,14 @@ void or_combine(int64_t n_dof, int nterm, const double* const* U,
  * density, max|divB|, L2(divB), max|psi|, nan flag, 0...}. */
 int or_diagnostics(const or_mesh* m, const or_params* p, const double* Q,
                    const double* ghost, double* out);
+
+/* Spherical-component diagnostics (Sec. "Results"): per (r, theta) bin of
+ * n_r x n_th uniform bins (r in [rb, rt], theta in [0, pi]) the sums over
+ * the SPs in the bin of w, w V_phi, w V_mer, w (B_r^2 + B_theta^2)/2 and
+ * w B_phi^2/2 (w = quadrature weight x |J|) into out[n_r][n_th][5].
+ * Returns 0, or -1 for bad bin counts. */
+int or_sph_profiles(const or_mesh* m, const double* Q, double rb, double rt, int n_r, int n_th,
+                    double* out);
 
 /* Pointwise functions: inviscid and viscous flux through n for state q and
  * gradient G[v*3+j]; Rusanov common flux; fast speed along the unit nh;

@@ -70,3 +70,98 @@ def test_nan_flag(oracle):
     assert oracle.Mesh.diagnostics(m, oracle.make_params(), Q)[8] == 0.0
     Q[5, 2, 7] = np.inf
     assert oracle.Mesh.diagnostics(m, oracle.make_params(), Q)[8] == 1.0
+
+
+# --- spherical components (Sec. "Results": differential rotation, meridional
+# flow, poloidal and toroidal magnetic energy) ---------------------------------
+
+def _sph_frame(x):
+    """r_hat, theta_hat, phi_hat at points x [E][3][n] (test-side construction)."""
+    r = np.sqrt((x ** 2).sum(1))
+    rc = np.sqrt(x[:, 0] ** 2 + x[:, 1] ** 2)
+    rh = x / r[:, None]
+    ph = np.stack([-x[:, 1] / rc, x[:, 0] / rc, np.zeros_like(rc)], 1)
+    th = np.stack([x[:, 0] * x[:, 2] / (r * rc), x[:, 1] * x[:, 2] / (r * rc), -rc / r], 1)
+    return rh, th, ph
+
+
+def _flow_state(x, U, B):
+    rho = 1.0 + 0.3 * np.sin(3 * x[:, 0]) * np.cos(2 * x[:, 2])
+    return _state(x, lambda x: rho, lambda x: U, lambda x: np.full(rho.shape, 0.2), lambda x: B,
+                  lambda x: np.zeros(rho.shape))
+
+
+def test_sph_energy_split_sums_to_EB(oracle):
+    """(B_r^2 + B_theta^2)/2 + B_phi^2/2 = |B|^2/2 pointwise, so the two volume
+    averages add up to E_B of the diagnostics for any field."""
+    m = oracle.Mesh.shell(6, 2, 2)
+    x = m.get("x_sp")
+    rng = np.random.default_rng(5)
+    B = rng.normal(size=x.shape)
+    U = rng.normal(size=x.shape) * 0.1
+    Q = _flow_state(x, U, B)
+    d = oracle.Mesh.diagnostics(m, oracle.make_params(), Q)
+    P = m.sph_profiles(Q, 3, 5)
+    V = P[..., 0].sum()
+    assert abs(V - d[0]) <= 1e-13 * V
+    assert abs((P[..., 3].sum() + P[..., 4].sum()) / V - d[4]) <= 1e-13 * d[4]
+
+
+def test_sph_pure_fields(oracle):
+    """A purely toroidal field has no poloidal energy and vice versa; the dipole
+    of the initial condition is poloidal."""
+    m = oracle.Mesh.shell(6, 2, 2)
+    x = m.get("x_sp")
+    rh, th, ph = _sph_frame(x)
+    zero = np.zeros(x.shape)
+    for B, tor in ((0.7 * ph, True), (0.4 * rh, False), (0.3 * th, False)):
+        P = m.sph_profiles(_flow_state(x, zero, B), 2, 4)
+        c2 = (B ** 2).sum(1).max() / 2
+        if tor:
+            assert np.abs(P[..., 3]).max() <= 1e-14 * P[..., 0].max()
+            assert np.allclose(P[..., 4] / P[..., 0], c2, rtol=1e-13, atol=0)
+        else:
+            assert np.abs(P[..., 4]).max() <= 1e-14 * P[..., 0].max()
+            assert np.allclose(P[..., 3] / P[..., 0], c2, rtol=1e-13, atol=0)
+    r = np.sqrt((x ** 2).sum(1))
+    zh = np.array([0.0, 0.0, 1.0])[None, :, None]
+    dip = 1e-3 * (0.7 / r[:, None]) ** 3 * (3 * (rh * zh).sum(1, keepdims=True) * rh - zh)
+    P = m.sph_profiles(_flow_state(x, zero, dip), 2, 4)
+    assert np.abs(P[..., 4]).max() <= 1e-14 * np.abs(P[..., 3]).max()
+
+
+def test_sph_flows(oracle):
+    """Constant radial, polar and azimuthal flows: V_mer and V_phi bin averages
+    are the constants exactly (the azimuthal direction counter-clockwise about
+    +z); a solid-body rotation has no meridional flow and V_phi > 0."""
+    m = oracle.Mesh.shell(6, 2, 2)
+    x = m.get("x_sp")
+    rh, th, ph = _sph_frame(x)
+    zero = np.zeros(x.shape)
+    for U, vm, vp in ((0.05 * rh, 0.05, 0.0), (-0.03 * th, 0.03, 0.0), (0.02 * ph, 0.0, 0.02),
+                      (0.03 * rh + 0.04 * th, 0.05, 0.0)):
+        P = m.sph_profiles(_flow_state(x, U, zero), 3, 4)
+        assert np.allclose(P[..., 2] / P[..., 0], vm, rtol=1e-13, atol=1e-15)
+        assert np.allclose(P[..., 1] / P[..., 0], vp, rtol=1e-13, atol=1e-15)
+    Om = 0.12
+    U = Om * np.stack([-x[:, 1], x[:, 0], np.zeros_like(x[:, 0])], 1)
+    P = m.sph_profiles(_flow_state(x, U, zero), 3, 4)
+    assert np.abs(P[..., 2]).max() <= 1e-14 * P[..., 0].max()
+    assert (P[..., 1] > 0).all()
+
+
+def test_sph_bin_volumes(oracle):
+    """With the radial bins on the element layers (uniform in r) and the
+    theta bins split at the equator (an element boundary for even N_z), the
+    bins' summed weights are the volumes of the spherical-shell pieces, to
+    the mesh's geometric accuracy."""
+    m = oracle.Mesh.shell(6, 4, 3)
+    Q = np.zeros((m.E, 9, 216))
+    Q[:, 0] = 1.0
+    Q[:, 4] = 1.0
+    P = m.sph_profiles(Q, 3, 2)
+    rs = 0.70 + np.arange(4) * (0.98 - 0.70) / 3
+    for i in range(3):
+        vol_half = 2 * np.pi / 3 * (rs[i + 1] ** 3 - rs[i] ** 3)
+        assert abs(P[i, 0, 0] - vol_half) <= 1e-8 * vol_half
+        assert abs(P[i, 1, 0] - vol_half) <= 1e-8 * vol_half
