@@ -244,6 +244,37 @@ typedef struct {
   void* ws;
 } sdm_batch_item;
 
+/* ---------------- spherical-component diagnostics ---------------------- */
+
+/* The paper reports the differential rotation (longitude-time average of
+ * V_phi), the meridional flow (that of V_mer = sqrt(V_r^2 + V_theta^2)) and
+ * the poloidal / toroidal magnetic energies (B_r^2 + B_theta^2 and B_phi^2
+ * over 8 pi; 1/2 in the rationalized units of this library) (Sec.
+ * "Results").  The longitude average is taken per (r, theta) bin: n_r x n_th
+ * uniform bins, r in [rb, rt], theta = atan2(sqrt(x^2 + y^2), z) in [0, pi];
+ * solution point x lies in bin (ir, it) = (floor((|x| - rb)/(rt - rb) n_r),
+ * floor(theta/pi n_th)), clamped to the ranges.
+ *
+ * sdm_sph_bins (HOST, no GPU): groups the n_elem (p+1)^3 solution points of
+ * a mesh (x_sp: host [n_elem][3][(p+1)^3], as built by sdm_shell_build) by
+ * bin.  order (host, int32 [n_elem (p+1)^3]) receives the global SP indices
+ * e (p+1)^3 + sp bin by bin, ascending within a bin; offsets (host, int64
+ * [n_r n_th + 1]) the bin ranges, bin b = ir n_th + it.  SDM_EINVAL for bad
+ * sizes or more than 2^31 points.
+ *
+ * sdm_sph_profiles (DEVICE): for state Q ([E][9][N^3] FP64) of ctx's bound
+ * mesh and DEVICE copies of order / offsets (n_bins = n_r n_th), writes
+ * DEVICE out[n_bins][5]: the sums over the bin's SPs of w, w V_phi, w V_mer,
+ * w (B_r^2 + B_theta^2)/2 and w B_phi^2/2, w = quadrature weight x |J|
+ * (divide by the first for bin averages; sum over bins and divide by the
+ * volume for the energies).  On the polar axis phi_hat = (0, 1, 0).  FP64 in
+ * either arithmetic; bitwise reproducible (fixed summation order).  Time
+ * averages are the caller's (sum the outputs of several states). */
+sdm_status sdm_sph_bins(int64_t n_elem, int p, const double* x_sp, double rb, double rt, int n_r, int n_th,
+                        int32_t* order, int64_t* offsets);
+sdm_status sdm_sph_profiles(sdm_ctx* ctx, const double* Q, const int32_t* order, const int64_t* offsets,
+                            int n_bins, double* out, void* stream);
+
 /* Bytes of DEVICE scratch sdm_batch_stage needs for n_items runs (their
  * descriptor tables). */
 sdm_status sdm_batch_workspace_size(int n_items, size_t* bytes);

@@ -493,4 +493,25 @@ int box_build(int nx, int ny, int nz, double Lx, double Ly, double Lz, int perio
   return 0;
 }
 
+void sph_bins(int64_t E, int N, const double* x_sp, double rb, double rt, int n_r, int n_th, int32_t* order,
+              int64_t* offsets) {
+  const int64_t N3 = (int64_t)N * N * N, n = E * N3, nb = (int64_t)n_r * n_th;
+  std::vector<int32_t> bin(n);
+  for (int64_t g = 0; g < n; ++g) {
+    const int64_t e = g / N3, q = g % N3;
+    const double x = x_sp[(e * 3 + 0) * N3 + q], y = x_sp[(e * 3 + 1) * N3 + q], z = x_sp[(e * 3 + 2) * N3 + q];
+    const double r = std::sqrt(x * x + y * y + z * z), th = std::atan2(std::sqrt(x * x + y * y), z);
+    int ir = (int)std::floor((r - rb) / (rt - rb) * n_r), it = (int)std::floor(th / kPi * n_th);
+    ir = std::min(std::max(ir, 0), n_r - 1);
+    it = std::min(std::max(it, 0), n_th - 1);
+    bin[g] = ir * n_th + it;
+  }
+  // counting sort, stable in g
+  std::fill(offsets, offsets + nb + 1, 0);
+  for (int64_t g = 0; g < n; ++g) ++offsets[bin[g] + 1];
+  for (int64_t b = 0; b < nb; ++b) offsets[b + 1] += offsets[b];
+  std::vector<int64_t> next(offsets, offsets + nb);
+  for (int64_t g = 0; g < n; ++g) order[next[bin[g]]++] = (int32_t)g;
+}
+
 }  // namespace sdm

@@ -27,4 +27,10 @@ int shell_build(int Nz, int Nr, int p, double rb, double rt, double* x_sp, doubl
 int box_build(int nx, int ny, int nz, double Lx, double Ly, double Lz, int periodic, double warp,
               int p, double* x_sp, double* detJ, double* S_fp, double* S_sp, int32_t* nbr, double* n_face);
 
+// Solution points grouped by (r, theta) bin: bin of SP g (= e N^3 + sp) from
+// its position; order[] lists the SPs bin by bin (ascending g within a bin),
+// offsets[b] .. offsets[b + 1] is bin b's range.
+void sph_bins(int64_t E, int N, const double* x_sp, double rb, double rt, int n_r, int n_th, int32_t* order,
+              int64_t* offsets);
+
 }  // namespace sdm

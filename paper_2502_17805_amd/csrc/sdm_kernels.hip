@@ -710,7 +710,9 @@ void k_volume(Launch L) {
       double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       if (tid < N3) {
         const int sp = tid;
-        const double wq = (double)tb.W[ia0] * (double)tb.W[ia1] * (double)tb.W[ia2] * R.detJ[e * N3 + sp];
+        // FP64 quadrature weights in either arithmetic
+        const DevTab<double>& td = tab<double>(N);
+        const double wq = td.W[ia0] * td.W[ia1] * td.W[ia2] * R.detJ[e * N3 + sp];
         const GBL double* q = Qe + sp;
         const double rho = q[0];
         const double m2 = q[N3] * q[N3] + q[2 * N3] * q[2 * N3] + q[3 * N3] * q[3 * N3];
@@ -1027,6 +1029,69 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
 // ---------------------------------------------------------------------------
 // diagnostics reduction (one block, fixed order)
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// k_sph_profile: spherical-component sums of one (r, theta) bin per
+// workgroup (Sec. "Results": V_phi and V_mer = sqrt(V_r^2 + V_theta^2) for
+// the longitude averages, (B_r^2 + B_theta^2)/2 and B_phi^2/2 for the
+// poloidal and toroidal energies), weights W_a W_b W_c |J|.  Each thread
+// sums its strided share of the bin's SP list in list order, then a fixed
+// reduction tree: results are bitwise reproducible.  On the polar axis
+// phi_hat = (0, 1, 0) and theta_hat = (sign z, 0, 0).
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void k_sph_profile(const double* Q, const double* x_sp, const double* detJ,
+                                                     const int32_t* order, const int64_t* offsets, double* out) {
+  constexpr int N3 = N * N * N;
+  const DevTab<double>& tb = tab<double>(N);
+  const int64_t o0 = offsets[blockIdx.x], o1 = offsets[blockIdx.x + 1];
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t j = o0 + threadIdx.x; j < o1; j += 256) {
+    const int64_t g = order[j], e = g / N3;
+    const int q = (int)(g % N3);
+    const double w = tb.W[q % N] * tb.W[(q / N) % N] * tb.W[q / (N * N)] * detJ[e * N3 + q];
+    const double x = x_sp[(e * 3 + 0) * N3 + q], y = x_sp[(e * 3 + 1) * N3 + q], z = x_sp[(e * 3 + 2) * N3 + q];
+    const double rc = sqrt(x * x + y * y), r = sqrt(x * x + y * y + z * z);
+    const double rh[3] = {x / r, y / r, z / r};
+    double ph[3], th[3];
+    if (rc > 0.0) {
+      ph[0] = -y / rc; ph[1] = x / rc; ph[2] = 0.0;
+      th[0] = ph[1] * rh[2] - ph[2] * rh[1];
+      th[1] = ph[2] * rh[0] - ph[0] * rh[2];
+      th[2] = ph[0] * rh[1] - ph[1] * rh[0];
+    } else {
+      ph[0] = 0.0; ph[1] = 1.0; ph[2] = 0.0;
+      th[0] = z >= 0.0 ? 1.0 : -1.0; th[1] = 0.0; th[2] = 0.0;
+    }
+    const double* s = Q + e * 9 * N3 + q;
+    const double u[3] = {s[N3] / s[0], s[2 * N3] / s[0], s[3 * N3] / s[0]};
+    const double B[3] = {s[5 * N3], s[6 * N3], s[7 * N3]};
+    double ur = 0, ut = 0, up = 0, br = 0, bt = 0, bp = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ur += u[k] * rh[k]; ut += u[k] * th[k]; up += u[k] * ph[k];
+      br += B[k] * rh[k]; bt += B[k] * th[k]; bp += B[k] * ph[k];
+    }
+    acc[0] += w;
+    acc[1] += w * up;
+    acc[2] += w * sqrt(ur * ur + ut * ut);
+    acc[3] += w * 0.5 * (br * br + bt * bt);
+    acc[4] += w * 0.5 * bp * bp;
+  }
+  __shared__ double red[4][5];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double v = acc[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wv][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    const int k = threadIdx.x;
+    out[blockIdx.x * 5 + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_diag_reduce(const double* part, int64_t E, double* out) {
   __shared__ double s[256][9];
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -1581,6 +1646,39 @@ sdm_status sdm_diagnostics(sdm_ctx* c, const sdm_params* p, const double* Q, dou
   return SDM_OK;
 }
 
+
+sdm_status sdm_sph_bins(int64_t n_elem, int p, const double* x_sp, double rb, double rt, int n_r, int n_th,
+                        int32_t* order, int64_t* offsets) {
+  if (n_elem < 1 || p < 1 || p > kNMax - 1 || !x_sp || !order || !offsets)
+    return fail(SDM_EINVAL, "sph_bins: need n_elem >= 1, 1 <= p <= 7 and non-NULL buffers");
+  if (n_r < 1 || n_th < 1 || !(rt > rb)) return fail(SDM_EINVAL, "sph_bins: need n_r, n_th >= 1 and rt > rb");
+  const int64_t N = p + 1;
+  if (n_elem * N * N * N > INT32_MAX) return fail(SDM_EINVAL, "sph_bins: more than 2^31 solution points");
+  sph_bins(n_elem, (int)N, x_sp, rb, rt, n_r, n_th, order, offsets);
+  return SDM_OK;
+}
+
+sdm_status sdm_sph_profiles(sdm_ctx* c, const double* Q, const int32_t* order, const int64_t* offsets, int n_bins,
+                            double* out, void* stream) {
+  if (!c || !Q || !order || !offsets || !out) return fail(SDM_EINVAL, "sph_profiles: NULL argument");
+  if (!c->bound) return fail(SDM_ESTATE, "sph_profiles: no mesh bound");
+  if (n_bins < 1) return fail(SDM_EINVAL, "sph_profiles: n_bins >= 1 required");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  const double* x = c->mesh.x_sp;
+  const double* dj = c->mesh.detJ;
+  switch (c->N) {
+    case 2: hipLaunchKernelGGL(k_sph_profile<2>, dim3(n_bins), dim3(256), 0, s, Q, x, dj, order, offsets, out); break;
+    case 3: hipLaunchKernelGGL(k_sph_profile<3>, dim3(n_bins), dim3(256), 0, s, Q, x, dj, order, offsets, out); break;
+    case 4: hipLaunchKernelGGL(k_sph_profile<4>, dim3(n_bins), dim3(256), 0, s, Q, x, dj, order, offsets, out); break;
+    case 5: hipLaunchKernelGGL(k_sph_profile<5>, dim3(n_bins), dim3(256), 0, s, Q, x, dj, order, offsets, out); break;
+    case 6: hipLaunchKernelGGL(k_sph_profile<6>, dim3(n_bins), dim3(256), 0, s, Q, x, dj, order, offsets, out); break;
+    case 7: hipLaunchKernelGGL(k_sph_profile<7>, dim3(n_bins), dim3(256), 0, s, Q, x, dj, order, offsets, out); break;
+    default: return fail(SDM_EUNSUPPORTED, "sph_profiles: unsupported p");
+  }
+  HIP_TRY(hipGetLastError());
+  return SDM_OK;
+}
 
 sdm_status sdm_batch_workspace_size(int n_items, size_t* bytes) {
   if (n_items < 1 || !bytes) return fail(SDM_EINVAL, "batch_workspace_size: n_items >= 1 and bytes required");

@@ -1,13 +1,17 @@
 """Long runs of one seeded shell with diagnostics, in FP64 and FP32-mixed.
 
   python -m paper_2502_17805_amd.longrun --mesh 12,8 --p 5 --n-rho 3 --seed 1 \
-      --steps 1000 --every 50 [--arith 0,1] [--cfl 0.1]
+      --steps 1000 --every 50 [--arith 0,1] [--cfl 0.1] [--profiles 8,16]
 
 Prints one JSON line: for each arithmetic the diagnostics every `every` steps
 (mass, total energy, volume-averaged kinetic and magnetic energy, max and L2
 |div B|, max |psi|, NaN flag) and, when both arithmetics ran, the relative
 difference of KE, E_B and max|div B| of the FP32-mixed run from the FP64 run
-at each checkpoint.  Progress goes to stderr.
+at each checkpoint.  With --profiles n_r,n_th it also reports, per
+arithmetic, the poloidal and toroidal magnetic energies at each checkpoint
+and the longitude-time averages of V_phi (differential rotation) and V_mer
+(meridional flow) on n_r x n_th (r, theta) bins over the checkpoints after
+the first (Sec. "Results").  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -24,23 +28,45 @@ from . import sdmhd as sd
 DIAG_NAMES = ("volume", "mass", "energy", "KE", "E_B", "max_divB", "L2_divB", "max_psi", "nan")
 
 
-def run(mesh, Q, pr, dt, steps, every, arith, label=""):
+def run(mesh, Q, pr, dt, steps, every, arith, label="", bins=None):
     import torch
     s = sd.Solver(mesh, arith=arith)
     prm = sd.make_params(**pr)
     s.set_state(torch.from_numpy(Q))
     rows = [[0, 0.0] + list(s.diagnostics(prm)[:9])]
+    sph = {"E_Bpol": [], "E_Btor": []}
+    acc = None
+
+    def sample(k):
+        nonlocal acc
+        P = s.sph_profiles(bins)
+        V = P[..., 0].sum()
+        sph["E_Bpol"].append([k, P[..., 3].sum() / V])
+        sph["E_Btor"].append([k, P[..., 4].sum() / V])
+        if k > 0:
+            acc = P[..., :3].copy() if acc is None else acc + P[..., :3]
+
+    if bins is not None:
+        sample(0)
     t0 = time.perf_counter()
     for k in range(1, steps + 1):
         s.step(prm, dt)
         if k % every == 0 or k == steps:
             d = s.diagnostics(prm)
             rows.append([k, k * dt] + list(d[:9]))
+            if bins is not None:
+                sample(k)
             print(f"# {label} arith={arith} step {k}: KE={d[3]:.6e} E_B={d[4]:.6e} max|divB|={d[5]:.3e} "
                   f"nan={d[8]:g} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
             if d[8] != 0:
                 break
-    return rows
+    if bins is None:
+        return rows, None
+    if acc is not None:
+        w = np.where(acc[..., 0] > 0, acc[..., 0], 1.0)
+        sph["V_phi"] = (acc[..., 1] / w).tolist()
+        sph["V_mer"] = (acc[..., 2] / w).tolist()
+    return rows, sph
 
 
 def main(argv=None):
@@ -53,6 +79,8 @@ def main(argv=None):
     ap.add_argument("--every", type=int, default=50)
     ap.add_argument("--arith", default="0,1")
     ap.add_argument("--cfl", type=float, default=0.1)
+    ap.add_argument("--profiles", default="", metavar="N_R,N_TH",
+                    help="also report spherical-component diagnostics on n_r x n_th (r, theta) bins")
     a = ap.parse_args(argv)
     Nz, Nr = (int(x) for x in a.mesh.split(","))
     mesh = sd.shell(Nz, Nr, a.p)
@@ -65,8 +93,16 @@ def main(argv=None):
     label = f"shell 6x{Nz}x{Nz}x{Nr} p={a.p} N_rho={a.n_rho:g}"
     out = {"workload": f"{label}, seed {a.seed}, {a.steps} SSPRK(5,3) steps, CFL {a.cfl:g}",
            "elements": mesh.E, "dt": dt, "columns": ["step", "t", *DIAG_NAMES], "runs": {}}
+    bins = None
+    if a.profiles:
+        n_r, n_th = (int(x) for x in a.profiles.split(","))
+        bins = sd.sph_bins(mesh, n_r, n_th, bg.rb, bg.rt)
+        out["profile_bins"] = {"n_r": n_r, "n_th": n_th, "r": [bg.rb, bg.rt], "theta": [0.0, float(np.pi)]}
     for ar in (int(x) for x in a.arith.split(",")):
-        out["runs"]["fp64" if ar == 0 else "fp32-mixed"] = run(mesh, Q, pr, dt, a.steps, a.every, ar, label)
+        key = "fp64" if ar == 0 else "fp32-mixed"
+        out["runs"][key], sph = run(mesh, Q, pr, dt, a.steps, a.every, ar, label, bins)
+        if sph is not None:
+            out.setdefault("spherical", {})[key] = sph
     r = out["runs"]
     if "fp64" in r and "fp32-mixed" in r:
         rel = []

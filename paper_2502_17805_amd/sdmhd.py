@@ -88,6 +88,8 @@ _lib.sdm_rk_stage.argtypes = [_vp, C.POINTER(Params), C.POINTER(C.c_void_p), C.c
 _lib.sdm_rk_stage_volume.argtypes = _lib.sdm_rk_stage.argtypes
 _lib.sdm_rk_stage_finish.argtypes = _lib.sdm_rk_stage.argtypes
 _lib.sdm_diagnostics.argtypes = [_vp, C.POINTER(Params), _vp, _vp, _vp, _vp]
+_lib.sdm_sph_bins.argtypes = [C.c_int64, C.c_int, _vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp, _vp]
+_lib.sdm_sph_profiles.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp, _vp]
 _lib.sdm_batch_workspace_size.argtypes = [C.c_int, C.POINTER(C.c_size_t)]
 _lib.sdm_batch_stage.argtypes = [C.POINTER(BatchItem), C.c_int, _vp, C.c_size_t, C.c_int, _vp]
 _lib.sdm_profile_enable.argtypes = [_vp, C.c_int]
@@ -96,14 +98,15 @@ for _f in ("sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes", "sdm_box_build
            "sdm_create", "sdm_destroy", "sdm_mesh_bind", "sdm_workspace_size", "sdm_residual",
            "sdm_rk_stage", "sdm_diagnostics", "sdm_profile_enable", "sdm_profile_read",
            "sdm_batch_workspace_size", "sdm_batch_stage", "sdm_workspace_traces", "sdm_rk_stage_volume",
-           "sdm_rk_stage_finish"):
+           "sdm_rk_stage_finish", "sdm_sph_bins", "sdm_sph_profiles"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTED = ("sdm_last_error", "sdm_version", "sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes",
             "sdm_box_build", "sdm_tables", "sdm_create", "sdm_destroy", "sdm_mesh_bind",
             "sdm_workspace_size", "sdm_residual", "sdm_rk_stage", "sdm_diagnostics",
             "sdm_profile_enable", "sdm_profile_read", "sdm_batch_workspace_size", "sdm_batch_stage",
-            "sdm_workspace_traces", "sdm_rk_stage_volume", "sdm_rk_stage_finish")
+            "sdm_workspace_traces", "sdm_rk_stage_volume", "sdm_rk_stage_finish", "sdm_sph_bins",
+            "sdm_sph_profiles")
 KERNELS = ("traces", "volume", "volume_diag", "finish_residual", "finish_stage")
 
 
@@ -187,6 +190,27 @@ def box(nx, ny, nz, p, L=(1.0, 1.0, 1.0), periodic=7, warp=0.0) -> Mesh:
     _check(_lib.sdm_box_build(nx, ny, nz, L[0], L[1], L[2], periodic, warp, p, _p(m.x_sp), _p(m.detJ),
                               _p(m.S_fp), _p(m.Sj_sp), _p(m.nbr), _p(m.n_face)))
     return m
+
+
+@dataclasses.dataclass
+class SphBins:
+    """(r, theta) bins of a mesh's solution points (sdm_sph_bins): host order
+    and offsets; device copies are made on first use by a Solver."""
+    n_r: int
+    n_th: int
+    rb: float
+    rt: float
+    order: np.ndarray    # int32 [E N^3]
+    offsets: np.ndarray  # int64 [n_r n_th + 1]
+    _dev: tuple = None
+
+
+def sph_bins(mesh: Mesh, n_r: int, n_th: int, rb: float = 0.70, rt: float = 0.98) -> SphBins:
+    n = mesh.E * mesh.N ** 3
+    order = np.zeros(n, dtype=np.int32)
+    offsets = np.zeros(n_r * n_th + 1, dtype=np.int64)
+    _check(_lib.sdm_sph_bins(mesh.E, mesh.p, _p(mesh.x_sp), rb, rt, n_r, n_th, _p(order), _p(offsets)))
+    return SphBins(n_r, n_th, rb, rt, order, offsets)
 
 
 def face_point_map(N: int) -> np.ndarray:
@@ -416,6 +440,21 @@ class Solver:
         cnt = (C.c_int64 * 8)()
         _check(_lib.sdm_profile_read(self._h, ms, cnt))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNELS) if cnt[i]}
+
+    def sph_profiles(self, bins: SphBins, Q=None):
+        """Per (r, theta) bin: sums of w, w V_phi, w V_mer, w (B_r^2 + B_theta^2)/2,
+        w B_phi^2/2 over its solution points (sdm_sph_profiles), as a host
+        array (n_r, n_th, 5)."""
+        torch = self.torch
+        Q = self.regs[0] if Q is None else Q
+        if bins._dev is None or bins._dev[0] != self.dev:
+            bins._dev = (self.dev, torch.from_numpy(bins.order).to(self.dev),
+                         torch.from_numpy(bins.offsets).to(self.dev))
+        nb = bins.n_r * bins.n_th
+        out = torch.empty((nb, 5), dtype=torch.float64, device=self.dev)
+        _check(_lib.sdm_sph_profiles(self._h, Q.data_ptr(), bins._dev[1].data_ptr(), bins._dev[2].data_ptr(),
+                                     nb, out.data_ptr(), self._stream()))
+        return out.cpu().numpy().reshape(bins.n_r, bins.n_th, 5)
 
     def diagnostics(self, prm: Params, Q=None):
         Q = self.regs[0] if Q is None else Q

@@ -132,3 +132,32 @@ def test_patch_shard_import_faces(sd):
             if c >= 0:
                 e2, f2 = c >> 6, (c >> 3) & 7
                 assert (int(sh.mesh.nbr[e2, f2]) >> 6) == le
+
+
+def _bin_of(x, rb, rt, n_r, n_th):
+    """(r, theta) bin of each point of x [E][3][n] by the documented rule."""
+    r = np.sqrt((x ** 2).sum(1))
+    th = np.arctan2(np.sqrt(x[:, 0] ** 2 + x[:, 1] ** 2), x[:, 2])
+    ir = np.clip(np.floor((r - rb) / (rt - rb) * n_r).astype(int), 0, n_r - 1)
+    it = np.clip(np.floor(th / np.pi * n_th).astype(int), 0, n_th - 1)
+    return ir * n_th + it
+
+
+def test_sph_bins_host(sd, oracle):
+    """sdm_sph_bins: a stable grouping of every solution point by the
+    documented (r, theta) rule; the bin populations are those of the oracle
+    mesh's points under the same rule."""
+    m = sd.shell(2, 3, 5)
+    b = sd.sph_bins(m, 3, 4)
+    n = m.E * 216
+    assert len(b.order) == n and np.array_equal(np.sort(b.order), np.arange(n))
+    assert b.offsets[0] == 0 and b.offsets[-1] == n and (np.diff(b.offsets) >= 0).all()
+    bins = _bin_of(m.x_sp, 0.70, 0.98, 3, 4).reshape(-1)
+    for k in range(12):
+        seg = b.order[b.offsets[k]:b.offsets[k + 1]]
+        assert (bins[seg] == k).all() and (np.diff(seg) > 0).all()
+    xo = oracle.Mesh.shell(6, 2, 3).get("x_sp")
+    assert np.array_equal(np.bincount(_bin_of(xo, 0.70, 0.98, 3, 4).reshape(-1), minlength=12),
+                          np.diff(b.offsets))
+    with pytest.raises(sd.SdmError):
+        sd.sph_bins(m, 0, 4)
