@@ -10,7 +10,9 @@
  * named there.  Device work is hand-written HIP; every pointer marked
  * "device" must be device memory of the context's GPU, allocated and owned
  * by the caller (the library never frees it and allocates no device memory
- * except its static constant tables).  Calls that take a stream only enqueue
+ * except its static constant tables and, with the overlapped stage schedule
+ * of sdm_set_overlap, a 4-byte-per-element order table and a second stream
+ * per context).  Calls that take a stream only enqueue
  * work on it; results are valid after the stream is synchronised.
  *
  * Layouts (all row-major, last index fastest):
@@ -222,6 +224,38 @@ sdm_status sdm_rk_stage_volume(sdm_ctx* ctx, const sdm_params* prm, double* cons
                                const sdm_stage* stage, double dt, void* ws, void* stream);
 sdm_status sdm_rk_stage_finish(sdm_ctx* ctx, const sdm_params* prm, double* const* regs, int n_regs,
                                const sdm_stage* stage, double dt, void* ws, void* stream);
+
+/* Overlapped stage schedule.  A stage is two grid-wide passes: the volume
+ * pass of an element reads its face neighbours' traces of Q, and the finish
+ * pass reads their viscous face fluxes from the volume pass (Sec. "Spectral
+ * Difference Method": the common solution and the common viscous flux both
+ * couple face neighbours).  The volume pass is bound by arithmetic and
+ * latency, the finish pass by HBM bandwidth, so sdm_rk_stage may run them
+ * side by side on element chunks: chunk k's finish pass starts, on a second
+ * stream of the context, once the volume passes of every chunk holding a
+ * neighbour of chunk k are done.  Each element's arithmetic is unchanged, so
+ * the results are bitwise those of the plain schedule.
+ *
+ * sdm_element_chunks (HOST, no GPU): chunks of a mesh whose neighbour table
+ * nbr (host [n_elem][6], the layout above) is given.  Breadth-first levels
+ * over interior faces, seeded by the elements with a face in boundary group
+ * 0 (the inner wall of a shell: the levels are its radial layers) and, for a
+ * piece of the mesh without such a face, by its lowest element.  order
+ * (host int32 [n_elem]) receives the elements level by level, ascending
+ * within a level; chunk k is order[chunk_lo[k] .. chunk_lo[k + 1]) (host
+ * int64 [n_elem + 1] room), whole levels of at least min_chunk elements (a
+ * short last chunk joins the one before); chunk_dep[k] (host int32 [n_elem]
+ * room) is the last chunk holding a face neighbour of an element of chunk
+ * k (>= k); *n_chunks their number.  SDM_EINVAL for bad sizes or codes.
+ *
+ * sdm_set_overlap: min_chunk > 0 enables the schedule for the context's
+ * bound mesh with those chunks (2 or more; fewer leave it off), 0 disables
+ * it; *n_chunks (may be NULL) receives the number of chunks in use (0 =
+ * off).  Binding another mesh disables it.  sdm_rk_stage only: the split
+ * halves, sdm_residual, the diagnostics and batches run as before. */
+sdm_status sdm_element_chunks(int64_t n_elem, const int32_t* nbr, int64_t min_chunk, int32_t* order,
+                              int64_t* chunk_lo, int32_t* chunk_dep, int32_t* n_chunks);
+sdm_status sdm_set_overlap(sdm_ctx* ctx, int64_t min_chunk, int32_t* n_chunks);
 
 /* Diagnostics of state Q into DEVICE out[16] (FP64): volume, mass, total
  * energy, volume-averaged KE = (1/V) int rho|u|^2/2, E_B = (1/V) int

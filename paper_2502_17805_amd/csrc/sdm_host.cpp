@@ -515,3 +515,81 @@ void sph_bins(int64_t E, int N, const double* x_sp, double rb, double rt, int n_
 }
 
 }  // namespace sdm
+
+namespace sdm {
+
+int element_chunks(int64_t E, const int32_t* nbr, int64_t min_chunk, int32_t* order, std::vector<int64_t>& lo,
+                   std::vector<int32_t>& dep) {
+  if (E < 1 || min_chunk < 1) return 1;
+  // breadth-first levels over interior faces
+  std::vector<int32_t> level((size_t)E, -1);
+  std::vector<int64_t> queue;
+  queue.reserve((size_t)E);
+  for (int64_t e = 0; e < E; ++e)
+    for (int f = 0; f < 6; ++f) {
+      const int32_t c = nbr[e * 6 + f];
+      if (c < 0 && ((-(int64_t)c - 1) & 3) == 0 && level[e] < 0) {
+        level[e] = 0;
+        queue.push_back(e);
+      }
+    }
+  size_t head = 0;
+  int64_t next_seed = 0;
+  int32_t top = queue.empty() ? -1 : 0;  // highest level assigned so far
+  for (;;) {
+    while (head < queue.size()) {
+      const int64_t e = queue[head++];
+      for (int f = 0; f < 6; ++f) {
+        const int32_t c = nbr[e * 6 + f];
+        if (c < 0) continue;
+        const int64_t en = c >> 6;
+        if (level[en] < 0) {
+          level[en] = level[e] + 1;
+          top = std::max(top, level[en]);
+          queue.push_back(en);
+        }
+      }
+    }
+    // a piece not reached from the seeds starts at the next free level
+    while (next_seed < E && level[next_seed] >= 0) ++next_seed;
+    if (next_seed == E) break;
+    level[next_seed] = ++top;
+    queue.push_back(next_seed);
+  }
+  // order: level by level, ascending element index within a level
+  int32_t n_lev = 0;
+  for (int64_t e = 0; e < E; ++e) n_lev = std::max(n_lev, level[e] + 1);
+  std::vector<int64_t> cnt((size_t)n_lev + 1, 0);
+  for (int64_t e = 0; e < E; ++e) ++cnt[level[e] + 1];
+  for (int32_t l = 0; l < n_lev; ++l) cnt[l + 1] += cnt[l];
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  for (int64_t e = 0; e < E; ++e) order[pos[level[e]]++] = (int32_t)e;
+  // chunks of whole levels, each at least min_chunk elements (a short last
+  // chunk joins the one before it)
+  lo.assign(1, 0);
+  for (int32_t l = 0; l < n_lev; ++l)
+    if (cnt[l + 1] - lo.back() >= min_chunk) lo.push_back(cnt[l + 1]);
+  if (lo.back() != E) {
+    if (lo.size() > 1) lo.back() = E;
+    else lo.push_back(E);
+  }
+  const int K = (int)lo.size() - 1;
+  std::vector<int32_t> chunk_of((size_t)E);
+  for (int k = 0; k < K; ++k)
+    for (int64_t i = lo[k]; i < lo[k + 1]; ++i) chunk_of[order[i]] = k;
+  dep.assign((size_t)K, 0);
+  for (int k = 0; k < K; ++k) {
+    int32_t m = k;
+    for (int64_t i = lo[k]; i < lo[k + 1]; ++i) {
+      const int64_t e = order[i];
+      for (int f = 0; f < 6; ++f) {
+        const int32_t c = nbr[e * 6 + f];
+        if (c >= 0) m = std::max(m, chunk_of[c >> 6]);
+      }
+    }
+    dep[k] = m;
+  }
+  return 0;
+}
+
+}  // namespace sdm

@@ -93,8 +93,9 @@ struct Launch {
   const RunDesc* many;          // batched runs (device)
   const int64_t* prefix;        // [n_run + 1] element offsets of the runs
   int32_t n_run;
-  int64_t n_work;               // total elements
+  int64_t n_work;               // work items end here (one element each)
   int64_t w0;                   // first work item of this launch (one per workgroup)
+  const int32_t* order;         // single run: element of work item w (NULL: w itself)
 };
 
 // Device-side view of one run's descriptor with every array pointer in the
@@ -180,7 +181,7 @@ __device__ __forceinline__ Run<T> view(const Launch& L, int64_t w) {
   Run<T> r;
   if (L.many == nullptr) {
     fill_run(r, L.one);
-    r.e = w;
+    r.e = L.order ? (int64_t)((const GBL int32_t*)L.order)[w] : w;
     return r;
   }
   const GBL int64_t* pre = (const GBL int64_t*)L.prefix;
@@ -1211,7 +1212,25 @@ struct sdm_ctx {
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> marks;  // (kernel id, start event index)
+  // overlapped stage schedule (sdm_set_overlap): element chunks of whole
+  // breadth-first levels; chunk k's finish pass runs on `aux` once the volume
+  // passes of chunks 0..dep[k] are done, beside the later volume passes
+  int32_t* order = nullptr;        // device [E]: elements chunk by chunk
+  std::vector<int64_t> chunk_lo;   // [K + 1] ranges in `order`
+  std::vector<int32_t> chunk_dep;  // [K]
+  hipStream_t aux = nullptr;
+  std::vector<hipEvent_t> ev_vol;  // [K] volume pass of chunk k done
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
+
+namespace {
+void overlap_release(sdm_ctx* c) {
+  if (c->order) (void)hipFree(c->order);
+  c->order = nullptr;
+  c->chunk_lo.clear();
+  c->chunk_dep.clear();
+}
+}  // namespace
 
 namespace {
 
@@ -1278,7 +1297,7 @@ hipError_t launch_all(int which, const Launch& L, hipStream_t s, int64_t cap) {
   constexpr int BS = block_threads<N>();
   // at most `cap` workgroups per launch: consecutive launches cover the work
   const int64_t step = std::min<int64_t>(cap, (int64_t)1 << 30);
-  for (int64_t w0 = 0; w0 < L.n_work; w0 += step) {
+  for (int64_t w0 = L.w0; w0 < L.n_work; w0 += step) {
     Launch Lc = L;
     Lc.w0 = w0;
     const unsigned grid = (unsigned)std::min<int64_t>(L.n_work - w0, step);
@@ -1482,7 +1501,13 @@ sdm_status sdm_create(int device, int p, int arith, sdm_ctx** out) {
 
 sdm_status sdm_destroy(sdm_ctx* c) {
   if (c) {
+    (void)hipSetDevice(c->device);
     for (hipEvent_t h : c->ev) (void)hipEventDestroy(h);
+    overlap_release(c);
+    for (hipEvent_t h : c->ev_vol) (void)hipEventDestroy(h);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
   }
   delete c;
   return SDM_OK;
@@ -1537,9 +1562,60 @@ sdm_status sdm_mesh_bind(sdm_ctx* c, const sdm_mesh* m) {
       ++ng[g];
     }
   }
+  overlap_release(c);  // chunks belong to the previous mesh
   c->mesh = *m;
   for (int g = 0; g < 4; ++g) c->n_group[g] = ng[g];
   c->bound = true;
+  return SDM_OK;
+}
+
+sdm_status sdm_element_chunks(int64_t n_elem, const int32_t* nbr, int64_t min_chunk, int32_t* order,
+                              int64_t* chunk_lo, int32_t* chunk_dep, int32_t* n_chunks) {
+  if (n_elem < 1 || n_elem >= ((int64_t)1 << 25) || min_chunk < 1)
+    return fail(SDM_EINVAL, "element_chunks: 1 <= n_elem < 2^25 and min_chunk >= 1 required");
+  if (!nbr || !order || !chunk_lo || !chunk_dep || !n_chunks) return fail(SDM_EINVAL, "element_chunks: NULL argument");
+  for (int64_t i = 0; i < n_elem * 6; ++i)
+    if (nbr[i] >= 0 && ((nbr[i] >> 6) >= n_elem || ((nbr[i] >> 3) & 7) > 5))
+      return fail(SDM_EINVAL, "element_chunks: neighbour code out of range");
+  std::vector<int64_t> lo;
+  std::vector<int32_t> dep;
+  if (element_chunks(n_elem, nbr, min_chunk, order, lo, dep)) return fail(SDM_EINVAL, "element_chunks failed");
+  std::copy(lo.begin(), lo.end(), chunk_lo);
+  std::copy(dep.begin(), dep.end(), chunk_dep);
+  *n_chunks = (int32_t)dep.size();
+  return SDM_OK;
+}
+
+sdm_status sdm_set_overlap(sdm_ctx* c, int64_t min_chunk, int32_t* n_chunks) {
+  if (!c) return fail(SDM_EINVAL, "set_overlap: NULL context");
+  if (min_chunk < 0) return fail(SDM_EINVAL, "set_overlap: min_chunk >= 0 required");
+  HIP_TRY(hipSetDevice(c->device));
+  overlap_release(c);
+  if (n_chunks) *n_chunks = 0;
+  if (min_chunk == 0) return SDM_OK;
+  if (!c->bound) return fail(SDM_ESTATE, "set_overlap: no mesh bound");
+  const int64_t E = c->mesh.n_elem;
+  std::vector<int32_t> nb((size_t)E * 6), order((size_t)E);
+  HIP_TRY(hipMemcpy(nb.data(), c->mesh.nbr, sizeof(int32_t) * nb.size(), hipMemcpyDeviceToHost));
+  std::vector<int64_t> lo;
+  std::vector<int32_t> dep;
+  if (element_chunks(E, nb.data(), min_chunk, order.data(), lo, dep)) return fail(SDM_EINVAL, "set_overlap: chunking failed");
+  const int K = (int)dep.size();
+  if (K >= 2) {
+    HIP_TRY(hipMalloc(&c->order, sizeof(int32_t) * (size_t)E));
+    HIP_TRY(hipMemcpy(c->order, order.data(), sizeof(int32_t) * (size_t)E, hipMemcpyHostToDevice));
+    c->chunk_lo = lo;
+    c->chunk_dep = dep;
+    if (!c->aux) HIP_TRY(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    while ((int)c->ev_vol.size() < K) {
+      hipEvent_t h;
+      HIP_TRY(hipEventCreateWithFlags(&h, hipEventDisableTiming));
+      c->ev_vol.push_back(h);
+    }
+    if (!c->ev_in) HIP_TRY(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    if (!c->ev_out) HIP_TRY(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+  }
+  if (n_chunks) *n_chunks = K >= 2 ? K : 0;
   return SDM_OK;
 }
 
@@ -1605,6 +1681,37 @@ sdm_status stage_parts(sdm_ctx* c, const sdm_params* p, double* const* regs, int
   r.beta_dt = stg->beta * dt;
   r.write_traces = 1;
   Launch L = single(r);
+  if (parts == 3 && c->order) {
+    // overlapped schedule: volume passes chunk by chunk on the caller's
+    // stream; chunk k's finish pass on `aux` after the volume pass of chunk
+    // dep[k] (which completes every neighbour's viscous face flux and every
+    // read of chunk k's old face traces); the caller's stream then waits for
+    // the last finish pass
+    if (!stg->traces_valid && (st = run(c, 0, L, s)) != SDM_OK) return st;
+    const int K = (int)c->chunk_dep.size();
+    HIP_TRY(hipEventRecord(c->ev_in, s));
+    HIP_TRY(hipStreamWaitEvent(c->aux, c->ev_in, 0));
+    Launch Lc = L;
+    Lc.order = c->order;
+    int kf = 0;
+    for (int k = 0; k < K; ++k) {
+      Lc.w0 = c->chunk_lo[k];
+      Lc.n_work = c->chunk_lo[k + 1];
+      if ((st = run(c, 1, Lc, s)) != SDM_OK) return st;
+      if (kf < K && c->chunk_dep[kf] <= k) {
+        HIP_TRY(hipEventRecord(c->ev_vol[k], s));
+        HIP_TRY(hipStreamWaitEvent(c->aux, c->ev_vol[k], 0));
+      }
+      for (; kf < K && c->chunk_dep[kf] <= k; ++kf) {
+        Lc.w0 = c->chunk_lo[kf];
+        Lc.n_work = c->chunk_lo[kf + 1];
+        if ((st = run(c, 4, Lc, c->aux)) != SDM_OK) return st;
+      }
+    }
+    HIP_TRY(hipEventRecord(c->ev_out, c->aux));
+    HIP_TRY(hipStreamWaitEvent(s, c->ev_out, 0));
+    return SDM_OK;
+  }
   if (parts & 1) {
     if (!stg->traces_valid && (st = run(c, 0, L, s)) != SDM_OK) return st;
     if ((st = run(c, 1, L, s)) != SDM_OK) return st;

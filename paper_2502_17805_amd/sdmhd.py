@@ -90,6 +90,8 @@ _lib.sdm_rk_stage_finish.argtypes = _lib.sdm_rk_stage.argtypes
 _lib.sdm_diagnostics.argtypes = [_vp, C.POINTER(Params), _vp, _vp, _vp, _vp]
 _lib.sdm_sph_bins.argtypes = [C.c_int64, C.c_int, _vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp, _vp]
 _lib.sdm_sph_profiles.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp, _vp]
+_lib.sdm_element_chunks.argtypes = [C.c_int64, _vp, C.c_int64, _vp, _vp, _vp, C.POINTER(C.c_int32)]
+_lib.sdm_set_overlap.argtypes = [_vp, C.c_int64, C.POINTER(C.c_int32)]
 _lib.sdm_batch_workspace_size.argtypes = [C.c_int, C.POINTER(C.c_size_t)]
 _lib.sdm_batch_stage.argtypes = [C.POINTER(BatchItem), C.c_int, _vp, C.c_size_t, C.c_int, _vp]
 _lib.sdm_profile_enable.argtypes = [_vp, C.c_int]
@@ -98,7 +100,7 @@ for _f in ("sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes", "sdm_box_build
            "sdm_create", "sdm_destroy", "sdm_mesh_bind", "sdm_workspace_size", "sdm_residual",
            "sdm_rk_stage", "sdm_diagnostics", "sdm_profile_enable", "sdm_profile_read",
            "sdm_batch_workspace_size", "sdm_batch_stage", "sdm_workspace_traces", "sdm_rk_stage_volume",
-           "sdm_rk_stage_finish", "sdm_sph_bins", "sdm_sph_profiles"):
+           "sdm_rk_stage_finish", "sdm_sph_bins", "sdm_sph_profiles", "sdm_element_chunks", "sdm_set_overlap"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTED = ("sdm_last_error", "sdm_version", "sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes",
@@ -106,7 +108,7 @@ EXPORTED = ("sdm_last_error", "sdm_version", "sdm_shell_sizes", "sdm_shell_build
             "sdm_workspace_size", "sdm_residual", "sdm_rk_stage", "sdm_diagnostics",
             "sdm_profile_enable", "sdm_profile_read", "sdm_batch_workspace_size", "sdm_batch_stage",
             "sdm_workspace_traces", "sdm_rk_stage_volume", "sdm_rk_stage_finish", "sdm_sph_bins",
-            "sdm_sph_profiles")
+            "sdm_sph_profiles", "sdm_element_chunks", "sdm_set_overlap")
 KERNELS = ("traces", "volume", "volume_diag", "finish_residual", "finish_stage")
 
 
@@ -211,6 +213,19 @@ def sph_bins(mesh: Mesh, n_r: int, n_th: int, rb: float = 0.70, rt: float = 0.98
     offsets = np.zeros(n_r * n_th + 1, dtype=np.int64)
     _check(_lib.sdm_sph_bins(mesh.E, mesh.p, _p(mesh.x_sp), rb, rt, n_r, n_th, _p(order), _p(offsets)))
     return SphBins(n_r, n_th, rb, rt, order, offsets)
+
+
+def element_chunks(nbr: np.ndarray, min_chunk: int):
+    """Element chunks of the overlapped stage schedule (sdm_element_chunks):
+    (order int32 [E], chunk_lo int64 [K + 1], chunk_dep int32 [K])."""
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    E = nbr.shape[0]
+    order = np.zeros(E, dtype=np.int32)
+    lo = np.zeros(E + 1, dtype=np.int64)
+    dep = np.zeros(E, dtype=np.int32)
+    k = C.c_int32()
+    _check(_lib.sdm_element_chunks(E, _p(nbr), int(min_chunk), _p(order), _p(lo), _p(dep), C.byref(k)))
+    return order, lo[:k.value + 1].copy(), dep[:k.value].copy()
 
 
 def face_point_map(N: int) -> np.ndarray:
@@ -370,6 +385,13 @@ class Solver:
                 self._h = None
         except Exception:
             pass
+
+    def set_overlap(self, min_chunk: int) -> int:
+        """Enable (min_chunk > 0) or disable (0) the overlapped stage schedule
+        (sdm_set_overlap); returns the number of chunks in use (0 = off)."""
+        k = C.c_int32()
+        _check(_lib.sdm_set_overlap(self._h, int(min_chunk), C.byref(k)))
+        return k.value
 
     def trace_views(self):
         """(q_traces [E][6][9][N^2], v_traces [E][6][7][N^2]) as tensors viewing
