@@ -271,62 +271,98 @@ constexpr int row_stride() {
 }
 
 // Q and grad_x Q at one flux point from the point rows: one pass over the
-// line's N solution points accumulating all 36 fields; w[i * ws] are the
-// interpolation weights; optionally the radiative diffusivity sampled at
-// the SPs and interpolated the same way.
-template <int N, typename T>
-__device__ __forceinline__ void load_row(const T* sR, int sidx, T a[36]) {
-  constexpr int RS = row_stride<T>();
-  if constexpr (sizeof(T) == 8) {
-    const double2* row = reinterpret_cast<const double2*>(sR + sidx * RS);
+// line's N solution points accumulating all 36 fields (the first point's
+// products start the sums); w[i * ws] are the interpolation weights;
+// optionally the radiative diffusivity sampled at the SPs and interpolated
+// the same way.  The row reads are software-pipelined by half rows: the
+// second half of row i and the first half of row i + 1 are requested while
+// the previous half is accumulated, so LDS latency overlaps arithmetic with
+// no more registers than one row.
+template <typename T>
+struct RowVec;
+template <>
+struct RowVec<double> {
+  using V = double2;
+  static constexpr int W = 2;
+};
+template <>
+struct RowVec<float> {
+  using V = float4;
+  static constexpr int W = 4;
+};
+
+template <typename T, int K>
+__device__ __forceinline__ void lds_vecs(const T* p, typename RowVec<T>::V a[K]) {
+  const typename RowVec<T>::V* v = reinterpret_cast<const typename RowVec<T>::V*>(p);
 #pragma unroll
-    for (int j = 0; j < 18; ++j) {
-      const double2 x = row[j];
-      a[2 * j] = x.x;
-      a[2 * j + 1] = x.y;
-    }
-  } else {
-    const float4* row = reinterpret_cast<const float4*>(sR + sidx * RS);
+  for (int j = 0; j < K; ++j) a[j] = v[j];
+}
+
+__device__ __forceinline__ void vec_elems(const double2& v, double x[2]) {
+  x[0] = v.x;
+  x[1] = v.y;
+}
+__device__ __forceinline__ void vec_elems(const float4& v, float x[4]) {
+  x[0] = v.x;
+  x[1] = v.y;
+  x[2] = v.z;
+  x[3] = v.w;
+}
+
+// acc[base + ...] (=|+=) w * a, for the K vectors of a half row
+template <typename T, int K, bool FIRST>
+__device__ __forceinline__ void acc_vecs(T* acc, int base, T w, const typename RowVec<T>::V a[K]) {
+  constexpr int W = RowVec<T>::W;
 #pragma unroll
-    for (int j = 0; j < 9; ++j) {
-      const float4 x = row[j];
-      a[4 * j] = x.x;
-      a[4 * j + 1] = x.y;
-      a[4 * j + 2] = x.z;
-      a[4 * j + 3] = x.w;
+  for (int j = 0; j < K; ++j) {
+    T x[W];
+    vec_elems(a[j], x);
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      if (FIRST) acc[base + j * W + c] = w * x[c];
+      else acc[base + j * W + c] += w * x[c];
     }
   }
 }
 
-// Q and grad_x Q at one flux point from the point rows: one pass over the
-// line's N solution points accumulating all 36 fields (the first point's
-// products start the sums); w[i * ws] are the interpolation weights;
-// optionally the radiative diffusivity sampled at the SPs and interpolated
-// the same way.
 template <int N, typename T>
 __device__ __forceinline__ T interp_rows(const T* sR, const T* w, int ws, int s0, int st, T qf[9], T gf[27],
                                          bool use_kr, const Run<T>& R) {
   constexpr int N3 = N * N * N;
-  T kf = T(0);
-  {
-    const T w0 = w[0];
-    T a[36];
-    load_row<N>(sR, s0, a);
-#pragma unroll
-    for (int v = 0; v < 9; ++v) qf[v] = w0 * a[v];
-#pragma unroll
-    for (int k = 0; k < 27; ++k) gf[k] = w0 * a[9 + k];
-  }
+  constexpr int RS = row_stride<T>();
+  constexpr int W = RowVec<T>::W, NV = 36 / W, H0 = (NV + 1) / 2, H1 = NV - H0;
+  using V = typename RowVec<T>::V;
+  T acc[36];
+  V a0[H0], a1[H1];
+  // row 0; the weight of the next row is requested with its first half
+  T wc = w[0];
+  lds_vecs<T, H0>(sR + s0 * RS, a0);
+  lds_vecs<T, H1>(sR + s0 * RS + H0 * W, a1);
+  acc_vecs<T, H0, true>(acc, 0, wc, a0);
+  T wn = w[ws];
+  lds_vecs<T, H0>(sR + (s0 + st) * RS, a0);
+  acc_vecs<T, H1, true>(acc, H0 * W, wc, a1);
+  // rows 1 .. N-2: the next row's first half is requested before this
+  // row's second half is accumulated
 #pragma unroll 1
-  for (int i = 1; i < N; ++i) {
-    const T wi = w[i * ws];
-    T a[36];  // the row's 36 fields, 16 bytes per LDS read
-    load_row<N>(sR, s0 + i * st, a);
-#pragma unroll
-    for (int v = 0; v < 9; ++v) qf[v] += wi * a[v];
-#pragma unroll
-    for (int k = 0; k < 27; ++k) gf[k] += wi * a[9 + k];
+  for (int i = 1; i < N - 1; ++i) {
+    wc = wn;
+    lds_vecs<T, H1>(sR + (s0 + i * st) * RS + H0 * W, a1);
+    acc_vecs<T, H0, false>(acc, 0, wc, a0);
+    wn = w[(i + 1) * ws];
+    lds_vecs<T, H0>(sR + (s0 + (i + 1) * st) * RS, a0);
+    acc_vecs<T, H1, false>(acc, H0 * W, wc, a1);
   }
+  // row N-1
+  wc = wn;
+  lds_vecs<T, H1>(sR + (s0 + (N - 1) * st) * RS + H0 * W, a1);
+  acc_vecs<T, H0, false>(acc, 0, wc, a0);
+  acc_vecs<T, H1, false>(acc, H0 * W, wc, a1);
+#pragma unroll
+  for (int v = 0; v < 9; ++v) qf[v] = acc[v];
+#pragma unroll
+  for (int k = 0; k < 27; ++k) gf[k] = acc[9 + k];
+  T kf = T(0);
   if (use_kr) {
 #pragma unroll 1
     for (int i = 0; i < N; ++i) {
@@ -355,29 +391,33 @@ __device__ __forceinline__ void load_normal(const Run<T>& R, int f, int ab, T n[
 template <int N, typename T>
 __device__ __forceinline__ void load_outside_state(const Run<T>& R, int ab, int32_t code, T q[9]) {
   constexpr int N2 = N * N;
+  // one source pointer, then one block of loads
+  const GBL T* tn = nullptr;
+  const GBL double* gh = nullptr;
   if (code >= 0) {
     const int64_t en = code >> 6;
     const int fn = (code >> 3) & 7, o = code & 7;
     int a2, b2;
     omap<N>(o, ab % N, ab / N, a2, b2);
-    const GBL T* tn = R.Qtr + (en * 6 + fn) * 9 * N2 + a2 + N * b2;
-#pragma unroll
-    for (int v = 0; v < 9; ++v) q[v] = tn[v * N2];
+    tn = R.Qtr + (en * 6 + fn) * 9 * N2 + a2 + N * b2;
   } else {
     const int c2 = -code - 1, g = c2 & 3;
     const int64_t bf = c2 >> 2;
-    if (g == 3) {
-      const GBL T* tn = R.imp_q + bf * 9 * N2 + ab;
+    if (g == 3) tn = R.imp_q + bf * 9 * N2 + ab;
+    else if (g == 2 || wsel(g, R.P.wall_kind) == 1) gh = R.ghost + bf * 9 * N2 + ab;
+  }
+  if constexpr (sizeof(T) == 8) {
+    if (gh) tn = (const GBL T*)gh;  // the ghost state is FP64 like the traces
+  }
+  if (tn) {
 #pragma unroll
-      for (int v = 0; v < 9; ++v) q[v] = tn[v * N2];
-    } else if (g == 2 || wsel(g, R.P.wall_kind) == 1) {
-      const GBL double* gh = R.ghost + bf * 9 * N2 + ab;
+    for (int v = 0; v < 9; ++v) q[v] = tn[v * N2];
+  } else if (sizeof(T) != 8 && gh) {
 #pragma unroll
-      for (int v = 0; v < 9; ++v) q[v] = (T)gh[v * N2];
-    } else {
+    for (int v = 0; v < 9; ++v) q[v] = (T)gh[v * N2];
+  } else {
 #pragma unroll
-      for (int v = 0; v < 9; ++v) q[v] = T(0);
-    }
+    for (int v = 0; v < 9; ++v) q[v] = T(0);
   }
 }
 
@@ -519,10 +559,16 @@ void k_volume(Launch L) {
     //    position of this thread's SP (its state goes to its point row), the normal and outside state of this
     //    thread's face point, the metric at this thread's interior flux points
     //    of the three families, and the basis tables; then the LDS writes.
+    // the six neighbour codes are uniform across the workgroup: read through
+    // the scalar cache, so that the neighbour gather waits only for them and
+    // not (through the in-order vector-load counter) for the element's bulk
+    // loads
+    int32_t nbc[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) nbc[f] = nb6[f];
     int32_t fcode = 0;
     int lf = 0, lab = 0;  // this lane's face point (face passes)
     const bool has_face = FACE_REG && face_lane<N>(tid, lf, lab);
-    if (has_face) fcode = nb6[lf];
     T qv[9];
     if (tid < N3) {
 #pragma unroll
@@ -556,7 +602,12 @@ void k_volume(Launch L) {
       tD = tb.D[tid / (N + 1)][tid % (N + 1)];
     }
     if (tid < N * N) tDI = tb.DI[tid / N][tid % N];
-    if (has_face) load_outside_state<N>(R, lab, fcode, fq);
+    if (has_face) {
+      fcode = nbc[0];
+#pragma unroll
+      for (int f = 1; f < 6; ++f) fcode = lf == f ? nbc[f] : fcode;
+      load_outside_state<N>(R, lab, fcode, fq);
+    }
     if (tid < N3) {
 #pragma unroll
       for (int v = 0; v < 9; ++v) sR[tid * RS + v] = qv[v];
@@ -910,6 +961,56 @@ void k_volume(Launch L) {
   }
 }
 
+// the neighbour's viscous normal flux at face point `it` (face it / N^2) of
+// element e: its stored flux (orientation-mapped) or, on an import face, the
+// caller's; zero on walls and Dirichlet faces (completed in k_volume)
+template <int N, typename T>
+__device__ __forceinline__ void gather_vflux(const Run<T>& R, const int32_t nbc[6], int it, T fv[7]) {
+  constexpr int N2 = N * N;
+  const int f = it / N2, ab = it % N2;
+  int32_t code = nbc[0];
+#pragma unroll
+  for (int g = 1; g < 6; ++g) code = f == g ? nbc[g] : code;
+  const GBL T* src = nullptr;
+  if (code >= 0) {
+    const int64_t en = code >> 6;
+    const int fn = (code >> 3) & 7, o = code & 7;
+    int a2, b2;
+    omap<N>(o, ab % N, ab / N, a2, b2);
+    src = R.Vtr + (en * 6 + fn) * 7 * N2 + a2 + N * b2;
+  } else if (((-code - 1) & 3) == 3) {
+    src = R.imp_v + (int64_t)((-code - 1) >> 2) * 7 * N2 + ab;
+  }
+  if (src) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) fv[c] = src[c * N2];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) fv[c] = T(0);
+  }
+}
+
+// sum_k alpha_k u_k at solution point sp of element e over the stage's K
+// input registers, all K x 9 loads issued before the sums (FP64)
+template <int N, int K, typename T>
+__device__ __forceinline__ void rk_combine(const Run<T>& R, int64_t e, int sp, double u[9]) {
+  constexpr int N3 = N * N * N;
+  double a[K > 0 ? K : 1][9];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const GBL double* src = R.in[k] + e * 9 * N3 + sp;
+#pragma unroll
+    for (int v = 0; v < 9; ++v) a[k][v] = src[v * N3];
+  }
+#pragma unroll
+  for (int v = 0; v < 9; ++v) {
+    double x = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) x += R.alpha[k] * a[k][v];
+    u[v] = x;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // k_finish: neighbour half of the viscous common flux, then R or the stage
 // ---------------------------------------------------------------------------
@@ -929,55 +1030,57 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
     const Run<T> R = view<T>(L, w);
     const int64_t e = R.e;
     const GBL int32_t* nb6 = R.nbr + e * 6;
-    // this thread's SP: its own-element inputs are requested first (they do
-    // not depend on the gather): 1/|J|, the partial residual and, for a
-    // stage, the Shu-Osher combination sum_k alpha_k u_k of the registers
+    // the six neighbour codes (uniform: scalar loads, so that the gather
+    // does not wait for the own-element vector loads)
+    int32_t nbc[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) nbc[f] = nb6[f];
+    // the neighbours' viscous normal fluxes on the six faces: with one face
+    // point per thread they are requested first, into registers, so that
+    // they travel with the own-element loads below (one memory round trip)
+    constexpr bool GREG = 6 * N2 <= BS;
+    T fv[7];
+    if constexpr (GREG) {
+      if (tid < 6 * N2) gather_vflux<N>(R, nbc, tid, fv);
+    }
+    // this thread's SP: 1/|J|, the partial residual and, for a stage, the
+    // Shu-Osher combination sum_k alpha_k u_k of the registers
     const int sp = tid;
-    T ji = T(0), rpv[9];
+    T ji = T(0), rpv[9];  // |J| here; its reciprocal once the loads are issued
     double u[9];
     if (sp < N3) {
-      ji = recip((T)R.detJ[e * N3 + sp]);
+      ji = (T)R.detJ[e * N3 + sp];
       const GBL T* rp = R.Rp + e * 9 * N3 + sp;
 #pragma unroll
       for (int v = 0; v < 9; ++v) rpv[v] = rp[v * N3];
       if (STAGE) {
-#pragma unroll
-        for (int v = 0; v < 9; ++v) u[v] = 0.0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (k < R.n_in) {
-            const double a = R.alpha[k];
-            const GBL double* src = R.in[k] + e * 9 * N3 + sp;
-#pragma unroll
-            for (int v = 0; v < 9; ++v) u[v] += a * src[v * N3];
-          }
+        // every input register's loads issued before any is combined (one
+        // straight-line body per input count)
+        switch (R.n_in) {
+          case 1: rk_combine<N, 1>(R, e, sp, u); break;
+          case 2: rk_combine<N, 2>(R, e, sp, u); break;
+          case 3: rk_combine<N, 3>(R, e, sp, u); break;
+          case 4: rk_combine<N, 4>(R, e, sp, u); break;
+          default: rk_combine<N, 0>(R, e, sp, u); break;
         }
       }
     }
-    // the neighbours' viscous normal fluxes on the six faces
-    for (int it = tid; it < 6 * N2; it += BS) {
-      const int f = it / N2, ab = it % N2;
-      const int32_t code = nb6[f];
-      if (code >= 0) {
-        const int64_t en = code >> 6;
-        const int fn = (code >> 3) & 7, o = code & 7;
-        int a2, b2;
-        omap<N>(o, ab % N, ab / N, a2, b2);
-        const GBL T* src = R.Vtr + (en * 6 + fn) * 7 * N2 + a2 + N * b2;
+    if constexpr (GREG) {
+      if (tid < 6 * N2) {
 #pragma unroll
-        for (int c = 0; c < 7; ++c) sV[(f * 7 + c) * N2 + ab] = src[c * N2];
-      } else if (((-code - 1) & 3) == 3) {  // import face: the neighbour's flux as given
-        const GBL T* src = R.imp_v + (int64_t)((-code - 1) >> 2) * 7 * N2 + ab;
+        for (int c = 0; c < 7; ++c) sV[((tid / N2) * 7 + c) * N2 + tid % N2] = fv[c];
+      }
+    } else {
+      for (int it = tid; it < 6 * N2; it += BS) {
+        gather_vflux<N>(R, nbc, it, fv);
 #pragma unroll
-        for (int c = 0; c < 7; ++c) sV[(f * 7 + c) * N2 + ab] = src[c * N2];
-      } else {
-#pragma unroll
-        for (int c = 0; c < 7; ++c) sV[(f * 7 + c) * N2 + ab] = T(0);
+        for (int c = 0; c < 7; ++c) sV[((it / N2) * 7 + c) * N2 + it % N2] = fv[c];
       }
     }
     stage_tables<N>(sI, sD);
     __syncthreads();
     if (sp < N3) {
+      ji = recip(ji);
       const int ia[3] = {sp % N, (sp / N) % N, sp / N2};
       T corr[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
