@@ -278,6 +278,40 @@ typedef struct {
   void* ws;
 } sdm_batch_item;
 
+/* ---------------- initial background ----------------------------------- */
+
+/* Radial profiles of the initial state (Sec. "Initial Conditions"; U = 0,
+ * hydrostatic).  flux_balanced = 0: the polytrope of Eq. "polytrop eqns",
+ * T_b = (Phi_t - Phi_b) / (C_p (1 - exp(-(gamma - 1) N_rho))), Phi = -GM/r,
+ * p_b = rho_b Rgas T_b, C_p = gamma Rgas / (gamma - 1).  flux_balanced = 1:
+ * the almost flux-balanced profile built from it: the entropy gradient that
+ * makes the entropy-diffusion and radiative fluxes through the polytrope
+ * carry the luminosity L outward through every layer,
+ *   dS/dr = -(L / (4 pi r^2) + kappa_r rho0 C_p dT0/dr) / (kappa rho0 T0),
+ * integrated from the polytrope's entropy S_b at r_b, and the hydrostatic
+ * density d rho/dr = -(rho / C_p) dS/dr - (g / gamma) rho^(2 - gamma)
+ * exp(-gamma S / C_p) from rho(r_b) = rho_b (Eqs. "qfluxIC", "dSdr",
+ * "densityprofile", with the signs that make Eq. "qFlux" and hydrostatic
+ * balance hold); then p = rho^gamma exp(gamma S / C_p), T = p / (rho Rgas).
+ * kappa_r(r) = kr_scale (kr_c0 + kr_c1 w + kr_c2 w^2), w = r kr_omega_per_r.
+ * Solved by classical RK4 on 2^14 uniform steps with cubic Hermite
+ * interpolation between them (fourth order; host only, no GPU). */
+typedef struct {
+  double GM, Rgas, gamma;
+  double rb, rt;
+  double rho_b, N_rho;
+  double L;      /* luminosity through every layer */
+  double kappa;  /* thermal diffusivity (entropy diffusion) */
+  double kr_scale, kr_c0, kr_c1, kr_c2, kr_omega_per_r;
+  int32_t flux_balanced;
+} sdm_background;
+
+/* rho, p, T (host [n]) at the host radii r[n] in [rb, rt].  SDM_EINVAL for
+ * bad parameters, a radius outside the shell, or a flux-balanced density
+ * that reaches zero before r_t (no hydrostatic profile for that L). */
+sdm_status sdm_background_profile(const sdm_background* bg, int64_t n, const double* r, double* rho, double* p,
+                                  double* T);
+
 /* ---------------- spherical-component diagnostics ---------------------- */
 
 /* The paper reports the differential rotation (longitude-time average of

@@ -593,3 +593,104 @@ int element_chunks(int64_t E, const int32_t* nbr, int64_t min_chunk, int32_t* or
 }
 
 }  // namespace sdm
+
+// ---------------------------------------------------------------------------
+// initial background (Sec. "Initial Conditions")
+// ---------------------------------------------------------------------------
+namespace sdm {
+
+namespace {
+
+struct BgEval {
+  const Background& b;
+  double cp, T_b, p_b;
+  explicit BgEval(const Background& bg) : b(bg) {
+    cp = b.gamma * b.Rgas / (b.gamma - 1.0);
+    T_b = (b.GM / b.rb - b.GM / b.rt) / (cp * (1.0 - std::exp(-(b.gamma - 1.0) * b.N_rho)));
+    p_b = b.rho_b * b.Rgas * T_b;
+  }
+  // the polytrope: z = 1 - (Phi - Phi_b) / (C_p T_b), Phi = -GM / r
+  double z(double r) const { return 1.0 - (b.GM / b.rb - b.GM / r) / (cp * T_b); }
+  double kappa_r(double r) const {
+    const double w = r * b.kr_w;
+    return b.kr_scale * (b.kr_c0 + b.kr_c1 * w + b.kr_c2 * w * w);
+  }
+  // dS/dr from the outward heat flux L / (4 pi r^2) carried by entropy
+  // diffusion and radiation through the polytrope
+  double dSdr(double r) const {
+    const double zz = z(r);
+    const double rho0 = b.rho_b * std::pow(zz, 1.0 / (b.gamma - 1.0)), T0 = T_b * zz;
+    const double dT0 = -b.GM / (cp * r * r);
+    const double q = b.L / (4.0 * kPi * r * r);
+    return -(q + kappa_r(r) * rho0 * cp * dT0) / (b.kappa * rho0 * T0);
+  }
+  // (S, rho)' of the hydrostatic profile with entropy S: p = rho^gamma exp(gamma S / C_p)
+  void rhs(double r, const double y[2], double f[2]) const {
+    const double s = dSdr(r);
+    f[0] = s;
+    f[1] = -(y[1] / cp) * s - (b.GM / (r * r) / b.gamma) * std::pow(y[1], 2.0 - b.gamma) *
+                                  std::exp(-b.gamma * y[0] / cp);
+  }
+};
+
+}  // namespace
+
+int background_profile(const Background& b, int64_t n, const double* r, double* rho, double* p, double* T) {
+  if (!(b.gamma > 1.0) || !(b.Rgas > 0.0) || !(b.GM > 0.0) || !(b.rb > 0.0) || !(b.rt > b.rb) ||
+      !(b.rho_b > 0.0) || !(b.N_rho > 0.0) || n < 0)
+    return 1;
+  const double span = b.rt - b.rb;
+  for (int64_t i = 0; i < n; ++i)
+    if (!(r[i] >= b.rb - 1e-12 * span && r[i] <= b.rt + 1e-12 * span)) return 2;
+  const BgEval ev(b);
+  if (!b.flux_balanced) {
+    for (int64_t i = 0; i < n; ++i) {
+      const double zz = ev.z(r[i]);
+      rho[i] = b.rho_b * std::pow(zz, 1.0 / (b.gamma - 1.0));
+      p[i] = ev.p_b * std::pow(zz, b.gamma / (b.gamma - 1.0));
+      T[i] = ev.T_b * zz;
+    }
+    return 0;
+  }
+  if (!(b.kappa > 0.0)) return 1;
+  // classical RK4 on a uniform grid, then cubic Hermite interpolation with
+  // the exact derivatives at the nodes (both fourth order, h = span / 2^14)
+  const int M = 1 << 14;
+  const double h = span / M;
+  std::vector<double> Y(2 * (M + 1)), F(2 * (M + 1));
+  Y[0] = ev.cp * std::log(std::pow(ev.p_b, 1.0 / b.gamma) / b.rho_b);  // S_b of the polytrope
+  Y[1] = b.rho_b;
+  ev.rhs(b.rb, &Y[0], &F[0]);
+  for (int k = 0; k < M; ++k) {
+    const double r0 = b.rb + k * h;
+    const double* y = &Y[2 * k];
+    double k1[2], k2[2], k3[2], k4[2], t[2];
+    for (int c = 0; c < 2; ++c) k1[c] = F[2 * k + c];
+    for (int c = 0; c < 2; ++c) t[c] = y[c] + 0.5 * h * k1[c];
+    ev.rhs(r0 + 0.5 * h, t, k2);
+    for (int c = 0; c < 2; ++c) t[c] = y[c] + 0.5 * h * k2[c];
+    ev.rhs(r0 + 0.5 * h, t, k3);
+    for (int c = 0; c < 2; ++c) t[c] = y[c] + h * k3[c];
+    ev.rhs(r0 + h, t, k4);
+    for (int c = 0; c < 2; ++c) Y[2 * (k + 1) + c] = y[c] + h / 6.0 * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
+    if (!(Y[2 * (k + 1) + 1] > 0.0) || !std::isfinite(Y[2 * (k + 1)])) return 3;  // no hydrostatic profile
+    ev.rhs(r0 + h, &Y[2 * (k + 1)], &F[2 * (k + 1)]);
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    const double x = std::min(std::max(r[i], b.rb), b.rt);
+    int k = (int)std::floor((x - b.rb) / h);
+    k = std::min(std::max(k, 0), M - 1);
+    const double s = (x - (b.rb + k * h)) / h;
+    const double h00 = (1.0 + 2.0 * s) * (1.0 - s) * (1.0 - s), h10 = s * (1.0 - s) * (1.0 - s);
+    const double h01 = s * s * (3.0 - 2.0 * s), h11 = s * s * (s - 1.0);
+    double y[2];
+    for (int c = 0; c < 2; ++c)
+      y[c] = h00 * Y[2 * k + c] + h10 * h * F[2 * k + c] + h01 * Y[2 * (k + 1) + c] + h11 * h * F[2 * (k + 1) + c];
+    rho[i] = y[1];
+    p[i] = std::pow(y[1], b.gamma) * std::exp(b.gamma * y[0] / ev.cp);
+    T[i] = p[i] / (y[1] * b.Rgas);
+  }
+  return 0;
+}
+
+}  // namespace sdm

@@ -44,4 +44,16 @@ void sph_bins(int64_t E, int N, const double* x_sp, double rb, double rt, int n_
 int element_chunks(int64_t E, const int32_t* nbr, int64_t min_chunk, int32_t* order, std::vector<int64_t>& lo,
                    std::vector<int32_t>& dep);
 
+// Initial background of Sec. "Initial Conditions": the polytrope, or the
+// almost flux-balanced profile (entropy gradient from the outward heat flux
+// L / (4 pi r^2) through the polytrope, hydrostatic density from it).
+struct Background {
+  double GM, Rgas, gamma, rb, rt, rho_b, N_rho, L, kappa;
+  double kr_scale, kr_c0, kr_c1, kr_c2, kr_w;
+  int flux_balanced;
+};
+// (rho, p, T) at n radii in [rb, rt].  Nonzero: 1 bad parameters, 2 a radius
+// outside the shell, 3 the density of the flux-balanced profile reaches zero.
+int background_profile(const Background& b, int64_t n, const double* r, double* rho, double* p, double* T);
+
 }  // namespace sdm

@@ -1672,6 +1672,23 @@ sdm_status sdm_mesh_bind(sdm_ctx* c, const sdm_mesh* m) {
   return SDM_OK;
 }
 
+sdm_status sdm_background_profile(const sdm_background* bg, int64_t n, const double* r, double* rho, double* p,
+                                  double* T) {
+  if (!bg || n < 0 || (n > 0 && (!r || !rho || !p || !T))) return fail(SDM_EINVAL, "background_profile: NULL argument");
+  Background b;
+  b.GM = bg->GM; b.Rgas = bg->Rgas; b.gamma = bg->gamma; b.rb = bg->rb; b.rt = bg->rt;
+  b.rho_b = bg->rho_b; b.N_rho = bg->N_rho; b.L = bg->L; b.kappa = bg->kappa;
+  b.kr_scale = bg->kr_scale; b.kr_c0 = bg->kr_c0; b.kr_c1 = bg->kr_c1; b.kr_c2 = bg->kr_c2;
+  b.kr_w = bg->kr_omega_per_r; b.flux_balanced = bg->flux_balanced;
+  switch (background_profile(b, n, r, rho, p, T)) {
+    case 0: return SDM_OK;
+    case 2: return fail(SDM_EINVAL, "background_profile: radius outside [rb, rt]");
+    case 3: return fail(SDM_EINVAL, "background_profile: the flux-balanced density reaches zero (no hydrostatic profile)");
+    default: return fail(SDM_EINVAL, "background_profile: need gamma > 1, Rgas, GM, rho_b, N_rho > 0, 0 < rb < rt "
+                                     "and kappa > 0 for the flux-balanced profile");
+  }
+}
+
 sdm_status sdm_element_chunks(int64_t n_elem, const int32_t* nbr, int64_t min_chunk, int32_t* order,
                               int64_t* chunk_lo, int32_t* chunk_dep, int32_t* n_chunks) {
   if (n_elem < 1 || n_elem >= ((int64_t)1 << 25) || min_chunk < 1)

@@ -1,7 +1,7 @@
 """Long runs of one seeded shell with diagnostics, in FP64 and FP32-mixed.
 
   python -m paper_2502_17805_amd.longrun --mesh 12,8 --p 5 --n-rho 3 --seed 1 \
-      --steps 1000 --every 50 [--arith 0,1] [--cfl 0.1] [--profiles 8,16]
+      --steps 1000 --every 50 [--arith 0,1] [--cfl 0.1] [--profiles 8,16] [--setup solar]
 
 Prints one JSON line: for each arithmetic the diagnostics every `every` steps
 (mass, total energy, volume-averaged kinetic and magnetic energy, max and L2
@@ -11,7 +11,10 @@ at each checkpoint.  With --profiles n_r,n_th it also reports, per
 arithmetic, the poloidal and toroidal magnetic energies at each checkpoint
 and the longitude-time averages of V_phi (differential rotation) and V_mer
 (meridional flow) on n_r x n_th (r, theta) bins over the checkpoints after
-the first (Sec. "Results").  Progress goes to stderr.
+the first (Sec. "Results").  --setup solar runs the solar benchmark's parameters
+(section "Benchmark Problem Definition", in the units of inputs.py; N_rho 3
+or 4) on its shell from the flux-balanced background of the section
+"Initial Conditions".  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -81,16 +84,31 @@ def main(argv=None):
     ap.add_argument("--cfl", type=float, default=0.1)
     ap.add_argument("--profiles", default="", metavar="N_R,N_TH",
                     help="also report spherical-component diagnostics on n_r x n_th (r, theta) bins")
+    ap.add_argument("--setup", default="seeded", choices=("seeded", "solar"),
+                    help="seeded: the polytrope with seeded transport coefficients and heat input; solar: "
+                         "the solar benchmark's parameters on its flux-balanced background")
     a = ap.parse_args(argv)
     Nz, Nr = (int(x) for x in a.mesh.split(","))
-    mesh = sd.shell(Nz, Nr, a.p)
-    bg = inp.Background(a.n_rho)
-    Q = inp.shell_state(mesh.x_sp, bg, a.seed)
-    pr = inp.run_params(a.seed, bg)
+    if a.setup == "solar":
+        # the solar benchmark (N_rho = 3: first, 4: second) on its shell, from
+        # the library's flux-balanced background plus the seeded perturbations
+        sb = inp.solar_benchmark(a.n_rho)
+        bgk = {k: sb[k] for k in ("GM", "Rgas", "gamma", "rb", "rt", "rho_b", "N_rho", "L", "kappa",
+                                  "kr_scale", "kr_c0", "kr_c1", "kr_c2", "kr_omega_per_r")}
+        bg = inp.Background(a.n_rho, rb=sb["rb"], rt=sb["rt"])
+        mesh = sd.shell(Nz, Nr, a.p, bg.rb, bg.rt)
+        Q = inp.shell_state(mesh.x_sp, bg, a.seed, profile=lambda r: sd.background_profile(r, **bgk))
+        T_top = float(sd.background_profile(np.array([bg.rt]), **bgk)[2][0])
+        pr = inp.solar_run_params(sb, T_top)
+    else:
+        mesh = sd.shell(Nz, Nr, a.p)
+        bg = inp.Background(a.n_rho)
+        Q = inp.shell_state(mesh.x_sp, bg, a.seed)
+        pr = inp.run_params(a.seed, bg)
     ch = inp.glm_speed(Q)
     pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
     dt = inp.time_step(Q, mesh.Sj_sp, ch, a.cfl)
-    label = f"shell 6x{Nz}x{Nz}x{Nr} p={a.p} N_rho={a.n_rho:g}"
+    label = f"{a.setup} shell 6x{Nz}x{Nz}x{Nr} p={a.p} N_rho={a.n_rho:g}"
     out = {"workload": f"{label}, seed {a.seed}, {a.steps} SSPRK(5,3) steps, CFL {a.cfl:g}",
            "elements": mesh.E, "dt": dt, "columns": ["step", "t", *DIAG_NAMES], "runs": {}}
     bins = None

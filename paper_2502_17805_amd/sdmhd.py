@@ -61,6 +61,13 @@ class BatchItem(C.Structure):
                 ("n_regs", C.c_int32), ("stage", Stage), ("dt", C.c_double), ("ws", C.c_void_p)]
 
 
+class BackgroundDesc(C.Structure):
+    """Mirror of sdm_background."""
+    _fields_ = [(n, C.c_double) for n in ("GM", "Rgas", "gamma", "rb", "rt", "rho_b", "N_rho", "L", "kappa",
+                                          "kr_scale", "kr_c0", "kr_c1", "kr_c2", "kr_omega_per_r")] + [
+        ("flux_balanced", C.c_int32)]
+
+
 class MeshDesc(C.Structure):
     """Mirror of sdm_mesh."""
     _fields_ = [("n_elem", C.c_int64), ("n_bfaces", C.c_int64), ("x_sp", C.c_void_p),
@@ -90,6 +97,7 @@ _lib.sdm_rk_stage_finish.argtypes = _lib.sdm_rk_stage.argtypes
 _lib.sdm_diagnostics.argtypes = [_vp, C.POINTER(Params), _vp, _vp, _vp, _vp]
 _lib.sdm_sph_bins.argtypes = [C.c_int64, C.c_int, _vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp, _vp]
 _lib.sdm_sph_profiles.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp, _vp]
+_lib.sdm_background_profile.argtypes = [C.POINTER(BackgroundDesc), C.c_int64, _vp, _vp, _vp, _vp]
 _lib.sdm_element_chunks.argtypes = [C.c_int64, _vp, C.c_int64, _vp, _vp, _vp, C.POINTER(C.c_int32)]
 _lib.sdm_set_overlap.argtypes = [_vp, C.c_int64, C.POINTER(C.c_int32)]
 _lib.sdm_batch_workspace_size.argtypes = [C.c_int, C.POINTER(C.c_size_t)]
@@ -100,7 +108,8 @@ for _f in ("sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes", "sdm_box_build
            "sdm_create", "sdm_destroy", "sdm_mesh_bind", "sdm_workspace_size", "sdm_residual",
            "sdm_rk_stage", "sdm_diagnostics", "sdm_profile_enable", "sdm_profile_read",
            "sdm_batch_workspace_size", "sdm_batch_stage", "sdm_workspace_traces", "sdm_rk_stage_volume",
-           "sdm_rk_stage_finish", "sdm_sph_bins", "sdm_sph_profiles", "sdm_element_chunks", "sdm_set_overlap"):
+           "sdm_rk_stage_finish", "sdm_sph_bins", "sdm_sph_profiles", "sdm_element_chunks", "sdm_set_overlap",
+           "sdm_background_profile"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTED = ("sdm_last_error", "sdm_version", "sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes",
@@ -108,7 +117,7 @@ EXPORTED = ("sdm_last_error", "sdm_version", "sdm_shell_sizes", "sdm_shell_build
             "sdm_workspace_size", "sdm_residual", "sdm_rk_stage", "sdm_diagnostics",
             "sdm_profile_enable", "sdm_profile_read", "sdm_batch_workspace_size", "sdm_batch_stage",
             "sdm_workspace_traces", "sdm_rk_stage_volume", "sdm_rk_stage_finish", "sdm_sph_bins",
-            "sdm_sph_profiles", "sdm_element_chunks", "sdm_set_overlap")
+            "sdm_sph_profiles", "sdm_element_chunks", "sdm_set_overlap", "sdm_background_profile")
 KERNELS = ("traces", "volume", "volume_diag", "finish_residual", "finish_stage")
 
 
@@ -213,6 +222,19 @@ def sph_bins(mesh: Mesh, n_r: int, n_th: int, rb: float = 0.70, rt: float = 0.98
     offsets = np.zeros(n_r * n_th + 1, dtype=np.int64)
     _check(_lib.sdm_sph_bins(mesh.E, mesh.p, _p(mesh.x_sp), rb, rt, n_r, n_th, _p(order), _p(offsets)))
     return SphBins(n_r, n_th, rb, rt, order, offsets)
+
+
+def background_profile(r, GM=1.0, Rgas=1.0, gamma=5.0 / 3.0, rb=0.70, rt=0.98, rho_b=1.0, N_rho=3.0,
+                       L=0.0, kappa=0.0, kr_scale=0.0, kr_c0=0.0, kr_c1=0.0, kr_c2=0.0, kr_omega_per_r=0.0,
+                       flux_balanced=True):
+    """(rho, p, T) of the initial background at radii r (sdm_background_profile):
+    the flux-balanced profile, or the polytrope with flux_balanced=False."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    d = BackgroundDesc(GM, Rgas, gamma, rb, rt, rho_b, N_rho, L, kappa, kr_scale, kr_c0, kr_c1, kr_c2,
+                       kr_omega_per_r, 1 if flux_balanced else 0)
+    out = [np.empty_like(r) for _ in range(3)]
+    _check(_lib.sdm_background_profile(C.byref(d), r.size, _p(r), *[_p(o) for o in out]))
+    return tuple(out)
 
 
 def element_chunks(nbr: np.ndarray, min_chunk: int):

@@ -188,3 +188,42 @@ def test_mixed_precision_residual_bound(sd, oracle):
     ml, mo, bg, Q, pr = _c1(sd, oracle)
     rel = _check_residual(sd, oracle, ml, mo, Q, pr, arith=1, tol=1e-5)
     assert rel.max() > 1e-12  # really computed in FP32
+
+
+def test_residual_and_stage_solar_benchmark(sd, oracle):
+    """The solar benchmark's parameters (its shell radii, tiny diffusivities,
+    radiative diffusivity kappa_r(r) with the lambda reading, bottom heat flux
+    L / (4 pi r_b^2), radial-field top at the background's T_t) on the
+    oracle's flux-balanced background with the seeded perturbations: residual
+    and one fused stage against the oracle."""
+    import torch
+    from oracle import background as ob
+    sb = inp.solar_benchmark(3.0)
+    bgk = {k: sb[k] for k in ("GM", "Rgas", "gamma", "rb", "rt", "rho_b", "N_rho")}
+    c0, c1, c2, w = sb["kr_c0"], sb["kr_c1"], sb["kr_c2"], sb["kr_omega_per_r"]
+
+    def kr(r):
+        x = np.asarray(r) * w
+        return sb["kr_scale"] * (c0 + c1 * x + c2 * x * x)
+
+    prof = lambda r: ob.flux_balanced(r, L=sb["L"], kappa=sb["kappa"], kr=kr, **bgk)  # noqa: E731
+    bg = inp.Background(3.0, rb=sb["rb"], rt=sb["rt"])
+    ml = sd.shell(2, 2, 5, sb["rb"], sb["rt"])
+    mo = oracle.Mesh.shell(6, 2, 2, sb["rb"], sb["rt"])
+    Q = inp.shell_state(mo.get("x_sp"), bg, 4, profile=prof)
+    pr = inp.solar_run_params(sb, float(prof(np.array([sb["rt"]]))[2][0]))
+    ch = inp.glm_speed(Q)
+    pr.update(c_h=ch, glm_a=ch / (sb["rt"] - sb["rb"]))
+    _check_residual(sd, oracle, ml, mo, Q, pr)
+    # one SSPRK(5,3) stage 1: u1 = u0 + beta10 dt L(u0)
+    dt = inp.time_step(Q, mo.get("S_sp") / mo.get("detJ_sp")[:, None, None, :], ch, 0.1)
+    cur, inputs, beta, out = sd.ssp53_stages()[0]
+    s = sd.Solver(ml)
+    s.set_state(Q)
+    s.stage(sd.make_params(**pr), cur, inputs, beta, out, dt)
+    torch.cuda.synchronize()
+    got = s.regs[out].cpu().numpy()
+    Ro, ts = mo.residual(oracle.make_params(**pr), Q, with_scale=True)
+    want = Q + beta * dt * Ro
+    scale = np.abs(Q).max(axis=(0, 2)) + dt * ts
+    assert (np.abs(got - want).max(axis=(0, 2)) <= TOL * scale).all()

@@ -238,3 +238,36 @@ def test_element_chunks_disconnected(sd):
     chunk = _check_chunks(nbr, order, lo, dep, 1)
     assert set(chunk[layer == 0]) == {0}
     assert (chunk[layer > 0] > 0).all()
+
+
+@pytest.mark.parametrize("N_rho,L,kr", [(3.0, 0.0, 0.0), (3.0, 1e-6, 0.0), (5.0, 3e-7, 2e-6), (3.0, 8e-7, 5e-6)])
+def test_background_profile_matches_oracle(sd, N_rho, L, kr):
+    """sdm_background_profile (RK4 + Hermite) against the oracle's DOP853
+    solution of the same equations, and the polytrope against its closed form."""
+    from oracle import background as ob
+    base = dict(GM=1.0, Rgas=1.0, gamma=5.0 / 3.0, rb=0.70, rt=0.98, rho_b=1.0, N_rho=N_rho)
+    kr_c = dict(kr_scale=kr, kr_c0=1.5, kr_c1=-0.9, kr_c2=0.1, kr_omega_per_r=1.3)
+
+    def kr_fn(x):
+        w = x * 1.3
+        return kr * (1.5 - 0.9 * w + 0.1 * w * w)
+
+    r = np.concatenate([[0.70, 0.98], np.random.default_rng(5).uniform(0.70, 0.98, 200)])
+    got = sd.background_profile(r, L=L, kappa=1e-5, **base, **kr_c)
+    want = ob.flux_balanced(r, L=L, kappa=1e-5, kr=kr_fn, **base)
+    for a, b in zip(got, want[:3]):
+        np.testing.assert_allclose(a, b, rtol=1e-11)
+    poly = sd.background_profile(r, flux_balanced=False, **base)
+    for a, b in zip(poly, ob.polytrope(r, **base)):
+        np.testing.assert_allclose(a, b, rtol=1e-14)
+
+
+def test_background_profile_errors(sd):
+    with pytest.raises(sd.SdmError):
+        sd.background_profile(np.array([0.5]), L=1e-7, kappa=1e-5)  # below r_b
+    with pytest.raises(sd.SdmError):
+        sd.background_profile(np.array([0.8]), L=1e-7, kappa=0.0)  # no diffusivity
+    with pytest.raises(sd.SdmError):
+        sd.background_profile(np.array([0.8]), L=1e-3, kappa=1e-5)  # density reaches zero
+    with pytest.raises(sd.SdmError):
+        sd.background_profile(np.array([0.8]), rt=0.6, flux_balanced=False)
