@@ -333,6 +333,17 @@ __device__ __forceinline__ T interp_rows(const T* sR, const T* w, int ws, int s0
   constexpr int W = RowVec<T>::W, NV = 36 / W, H0 = (NV + 1) / 2, H1 = NV - H0;
   using V = typename RowVec<T>::V;
   T acc[36];
+  if constexpr (N <= 3) {
+    // short lines: plain row loop (the pipelined form spills registers here)
+    V a[NV];
+    lds_vecs<T, NV>(sR + s0 * RS, a);
+    acc_vecs<T, NV, true>(acc, 0, w[0], a);
+#pragma unroll 1
+    for (int i = 1; i < N; ++i) {
+      lds_vecs<T, NV>(sR + (s0 + i * st) * RS, a);
+      acc_vecs<T, NV, false>(acc, 0, w[i * ws], a);
+    }
+  } else {
   V a0[H0], a1[H1];
   // row 0; the weight of the next row is requested with its first half
   T wc = w[0];
@@ -358,6 +369,7 @@ __device__ __forceinline__ T interp_rows(const T* sR, const T* w, int ws, int s0
   lds_vecs<T, H1>(sR + (s0 + (N - 1) * st) * RS + H0 * W, a1);
   acc_vecs<T, H0, false>(acc, 0, wc, a0);
   acc_vecs<T, H1, false>(acc, H0 * W, wc, a1);
+  }
 #pragma unroll
   for (int v = 0; v < 9; ++v) qf[v] = acc[v];
 #pragma unroll
@@ -965,12 +977,12 @@ void k_volume(Launch L) {
 // element e: its stored flux (orientation-mapped) or, on an import face, the
 // caller's; zero on walls and Dirichlet faces (completed in k_volume)
 template <int N, typename T>
-__device__ __forceinline__ void gather_vflux(const Run<T>& R, const int32_t nbc[6], int it, T fv[7]) {
+__device__ __forceinline__ void gather_vflux(const Run<T>& R, const GBL int32_t* nb6, int it, T fv[7]) {
   constexpr int N2 = N * N;
   const int f = it / N2, ab = it % N2;
-  int32_t code = nbc[0];
-#pragma unroll
-  for (int g = 1; g < 6; ++g) code = f == g ? nbc[g] : code;
+  // per-lane code load: selecting among six uniform codes by the lane's face
+  // is folded by the compiler into a private array in scratch memory
+  const int32_t code = nb6[f];
   const GBL T* src = nullptr;
   if (code >= 0) {
     const int64_t en = code >> 6;
@@ -1030,18 +1042,13 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
     const Run<T> R = view<T>(L, w);
     const int64_t e = R.e;
     const GBL int32_t* nb6 = R.nbr + e * 6;
-    // the six neighbour codes (uniform: scalar loads, so that the gather
-    // does not wait for the own-element vector loads)
-    int32_t nbc[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) nbc[f] = nb6[f];
     // the neighbours' viscous normal fluxes on the six faces: with one face
     // point per thread they are requested first, into registers, so that
     // they travel with the own-element loads below (one memory round trip)
     constexpr bool GREG = 6 * N2 <= BS;
     T fv[7];
     if constexpr (GREG) {
-      if (tid < 6 * N2) gather_vflux<N>(R, nbc, tid, fv);
+      if (tid < 6 * N2) gather_vflux<N>(R, nb6, tid, fv);
     }
     // this thread's SP: 1/|J|, the partial residual and, for a stage, the
     // Shu-Osher combination sum_k alpha_k u_k of the registers
@@ -1072,7 +1079,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
       }
     } else {
       for (int it = tid; it < 6 * N2; it += BS) {
-        gather_vflux<N>(R, nbc, it, fv);
+        gather_vflux<N>(R, nb6, it, fv);
 #pragma unroll
         for (int c = 0; c < 7; ++c) sV[((it / N2) * 7 + c) * N2 + it % N2] = fv[c];
       }
