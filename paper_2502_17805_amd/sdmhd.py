@@ -12,6 +12,9 @@ Entry points mirror include/sdmhd.h:
   Solver.stage(prm, regs, st, dt)  one fused Shu-Osher stage (sdm_rk_stage)
   Solver.step(prm, dt)             one SSPRK(5,3) step = five stages
   Solver.diagnostics(prm, Q)       volume, mass, energy, KE, E_B, div B, ...
+  sph_bins / Solver.sph_profiles   spherical-component sums per (r, theta) bin
+  background_profile(r, ...)       polytrope / flux-balanced initial background
+  Solver.set_overlap(min_chunk)    opt-in overlapped stage schedule
 """
 from __future__ import annotations
 
