@@ -61,18 +61,31 @@ def alg_bytes(kind, N, E, n_extra=1.2):
     return None if per is None else per * E
 
 
+# FP64 operations (+, -, *, /, sqrt) of one call of each pointwise physics
+# function of the kernels, counted on the host from sdm_physics.hpp
+# (tests/flops/count_physics_flops.cpp; tests/test_flop_count.py keeps them
+# in step with the source)
+PHYS_FLOPS = {"flux_inviscid": 83, "viscous_local": 197, "flux_viscous7": 54, "rusanov": 329}
+
+
 def alg_flops(N):
-    """FP64 flops of one residual evaluation per element, estimated from the
-    operations of the SD scheme (Sec. 3): the four tensor contractions
-    (Q to the flux points of each family, the derivative of the flux-point
-    polynomial at the SPs, the 27 gradient components to the flux points,
-    the flux divergence) as multiply-adds, the chain rule, and the pointwise
-    work per flux point (inviscid + viscous flux and its contraction with
-    S^d, about 300 flops), per face point (Rusanov + BR1, about 150) and per
-    SP (sources and update, about 100)."""
+    """FP64 flops of one residual evaluation per element (Sec. "Spectral
+    Difference Method"): the tensor contractions as multiply-adds (Q to the
+    flux points of each family, the derivative of the flux-point polynomial
+    at the SPs, the 27 gradient components to the flux points, the flux
+    divergence, the chain rule), plus the pointwise physics counted from the
+    kernels' own formulas: per interior flux point the inviscid and viscous
+    fluxes through S^d (flux_inviscid + viscous_local + flux_viscous7 + 7),
+    per unique face point the Rusanov flux and both sides' viscous fluxes with
+    their average (rusanov + 2 (viscous_local + flux_viscous7) + 21), per SP
+    the sources and the scaling by 1/|J| (67).  Wall faces are counted as
+    interior faces; the RK update is not part of the residual."""
     N2, N3, NF = N * N, N ** 3, (N + 1) * N * N
     mac = 3 * 9 * NF * N + 3 * 9 * N3 * (N + 1) + 27 * 3 * NF * N + 3 * 9 * N3 * (N + 1) + 27 * 3 * N3
-    point = 300 * 3 * NF + 150 * 6 * N2 // 2 + 100 * N3
+    f = PHYS_FLOPS
+    interior = f["flux_inviscid"] + f["viscous_local"] + f["flux_viscous7"] + 7
+    face = f["rusanov"] + 2 * (f["viscous_local"] + f["flux_viscous7"]) + 21
+    point = interior * 3 * N2 * (N - 1) + face * 3 * N2 + 67 * N3
     return 2 * mac + point
 
 
