@@ -173,6 +173,25 @@ def run_shard(sd, mesh, Q, pr, dt, steps, warmup, overlap):
             "value": dof * 5 / (ms * 1e-3), "unit": "DOF*RK-stage updates/s", "overlap_chunks": chunks}
 
 
+def run_serving(n_requests, ariths):
+    """The served ensemble: n_requests runs arriving as a Poisson process
+    (mean gap 20 ms), shells 6 x {4,8,12}^2 x {3,4,8}, p in {3,5}, N_rho in
+    {3,5}, 500 SSPRK(5,3) steps each, admitted by a 200 GB HBM budget and a
+    cap of 32,768 resident elements, with continuous batching of their
+    stages; completion-latency percentiles and aggregate DOF x RK-stage
+    throughput per arithmetic."""
+    from paper_2502_17805_amd import serve
+    res = {}
+    for arith in ariths:
+        reqs = serve.poisson_requests(n_requests, 0.020, 500, arith=arith)
+        results, st = serve.Server(budget_bytes=200e9, max_slots=64, max_elements=32768).run(reqs)
+        res["fp64" if arith == 0 else "fp32_mixed"] = dict(
+            requests=st["requests"], p50_latency_s=st["p50_latency_s"], p99_latency_s=st["p99_latency_s"],
+            dof_stage_per_s=st["dof_stage_per_s"], makespan_s=st["makespan_s"], peak_active=st["peak_active"],
+            nan_results=int(sum(r.diag[8] != 0 for r in results)))
+    return res
+
+
 def copy_rate(torch, nbytes=1 << 30, reps=5):
     """Device-to-device copy rate (GB/s, bytes read + written) of a plain
     1 GiB copy: the practical HBM streaming rate the stage is compared to."""
@@ -216,6 +235,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-shard", action="store_true")
     ap.add_argument("--cfl", type=float, default=0.1)
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="served-ensemble leg: that many Poisson-arriving runs of 500 steps (0: skip)")
     ap.add_argument("--overlap", type=int, default=0, metavar="MIN_CHUNK",
                     help="time the overlapped stage schedule (element chunks of at least MIN_CHUNK elements, "
                          "whole radial layers) beside the plain one; 0 = plain schedule only (the default: "
@@ -346,6 +367,11 @@ def main():
                              "kernels_ms_per_step_plain": {k: v[0] / r1["prof_steps"]
                                                            for k, v in r1["prof"].items()},
                              "speedup_vs_fp64": ms / ms1}
+    if args.serve_requests > 0:
+        out["serving"] = run_serving(args.serve_requests, (0,) if args.no_mixed else (0, 1))
+        for k, v in out["serving"].items():
+            print(f"# serving {k}: p50 {v['p50_latency_s']:.2f} s, p99 {v['p99_latency_s']:.2f} s, "
+                  f"{v['dof_stage_per_s']:.3e} DOF-stage/s", file=sys.stderr, flush=True)
     if not args.no_shard and args.config != "shell_48_p5":
         out["shard_6way"] = run_shard(sd, mesh, Q, pr, dt, args.steps, args.warmup, args.overlap)
         print(f"# shard: {out['shard_6way']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
