@@ -22,6 +22,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -89,10 +90,13 @@ def alg_flops(N):
     return 2 * mac + point
 
 
-def kernel_source_hash():
+def kernel_source_hash(root=ROOT):
+    """Hash of the kernel sources with runs of whitespace collapsed, so that a
+    formatting-only edit does not invalidate counters taken on the code."""
     h = hashlib.sha256()
     for f in ("sdm_kernels.hip", "sdm_physics.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_2502_17805_amd", "csrc", f), "rb").read())
+        data = open(os.path.join(root, "paper_2502_17805_amd", "csrc", f), "rb").read()
+        h.update(re.sub(rb"\s+", b" ", data))
     return h.hexdigest()[:16]
 
 

@@ -344,31 +344,31 @@ __device__ __forceinline__ T interp_rows(const T* sR, const T* w, int ws, int s0
       acc_vecs<T, NV, false>(acc, 0, w[i * ws], a);
     }
   } else {
-  V a0[H0], a1[H1];
-  // row 0; the weight of the next row is requested with its first half
-  T wc = w[0];
-  lds_vecs<T, H0>(sR + s0 * RS, a0);
-  lds_vecs<T, H1>(sR + s0 * RS + H0 * W, a1);
-  acc_vecs<T, H0, true>(acc, 0, wc, a0);
-  T wn = w[ws];
-  lds_vecs<T, H0>(sR + (s0 + st) * RS, a0);
-  acc_vecs<T, H1, true>(acc, H0 * W, wc, a1);
-  // rows 1 .. N-2: the next row's first half is requested before this
-  // row's second half is accumulated
+    V a0[H0], a1[H1];
+    // row 0; the weight of the next row is requested with its first half
+    T wc = w[0];
+    lds_vecs<T, H0>(sR + s0 * RS, a0);
+    lds_vecs<T, H1>(sR + s0 * RS + H0 * W, a1);
+    acc_vecs<T, H0, true>(acc, 0, wc, a0);
+    T wn = w[ws];
+    lds_vecs<T, H0>(sR + (s0 + st) * RS, a0);
+    acc_vecs<T, H1, true>(acc, H0 * W, wc, a1);
+    // rows 1 .. N-2: the next row's first half is requested before this
+    // row's second half is accumulated
 #pragma unroll 1
-  for (int i = 1; i < N - 1; ++i) {
+    for (int i = 1; i < N - 1; ++i) {
+      wc = wn;
+      lds_vecs<T, H1>(sR + (s0 + i * st) * RS + H0 * W, a1);
+      acc_vecs<T, H0, false>(acc, 0, wc, a0);
+      wn = w[(i + 1) * ws];
+      lds_vecs<T, H0>(sR + (s0 + (i + 1) * st) * RS, a0);
+      acc_vecs<T, H1, false>(acc, H0 * W, wc, a1);
+    }
+    // row N-1
     wc = wn;
-    lds_vecs<T, H1>(sR + (s0 + i * st) * RS + H0 * W, a1);
+    lds_vecs<T, H1>(sR + (s0 + (N - 1) * st) * RS + H0 * W, a1);
     acc_vecs<T, H0, false>(acc, 0, wc, a0);
-    wn = w[(i + 1) * ws];
-    lds_vecs<T, H0>(sR + (s0 + (i + 1) * st) * RS, a0);
     acc_vecs<T, H1, false>(acc, H0 * W, wc, a1);
-  }
-  // row N-1
-  wc = wn;
-  lds_vecs<T, H1>(sR + (s0 + (N - 1) * st) * RS + H0 * W, a1);
-  acc_vecs<T, H0, false>(acc, 0, wc, a0);
-  acc_vecs<T, H1, false>(acc, H0 * W, wc, a1);
   }
 #pragma unroll
   for (int v = 0; v < 9; ++v) qf[v] = acc[v];
