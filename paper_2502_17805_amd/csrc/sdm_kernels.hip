@@ -1138,9 +1138,6 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
 }
 
 // ---------------------------------------------------------------------------
-// diagnostics reduction (one block, fixed order)
-// ---------------------------------------------------------------------------
-// ---------------------------------------------------------------------------
 // k_sph_profile: spherical-component sums of one (r, theta) bin per
 // workgroup (Sec. "Results": V_phi and V_mer = sqrt(V_r^2 + V_theta^2) for
 // the longitude averages, (B_r^2 + B_theta^2)/2 and B_phi^2/2 for the
@@ -1203,6 +1200,9 @@ __global__ __launch_bounds__(256) void k_sph_profile(const double* Q, const doub
   }
 }
 
+// ---------------------------------------------------------------------------
+// diagnostics reduction (one block, fixed order)
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_diag_reduce(const double* part, int64_t E, double* out) {
   __shared__ double s[256][9];
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
