@@ -217,6 +217,40 @@ def copy_rate(torch, nbytes=1 << 30, reps=5):
     return 2 * nbytes * reps / (ms * 1e-3) / 1e9
 
 
+_SINGLE_CORE_CHILD = """
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+from oracle import oracle as o
+from paper_2502_17805_amd import inputs as inp
+Nz, Nr, p, N_rho, seed = json.loads(sys.argv[2])
+m = o.Mesh.shell(p + 1, Nz, Nr)
+bg = inp.Background(N_rho)
+Q = inp.shell_state(m.get("x_sp"), bg, seed)
+pr = inp.run_params(seed, bg)
+ch = inp.glm_speed(Q)
+pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
+t0 = time.perf_counter()
+m.residual(o.make_params(**pr), Q)
+t = time.perf_counter() - t0
+print(json.dumps({"E": m.E, "seconds": t, "threads": o.threads()}))
+"""
+
+
+def cpu_single_core(Nz=12, Nr=8, p=5, N_rho=5.0, seed=3):
+    """The oracle on one host core: one residual evaluation (the work of one
+    RK stage) of the 6,912-element shell, in a child process started with
+    OMP_NUM_THREADS=1 (the thread count is fixed when OpenMP starts)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _SINGLE_CORE_CHILD, ROOT, json.dumps([Nz, Nr, p, N_rho, seed])],
+                       env=env, capture_output=True, text=True, timeout=300, check=True)
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": d["E"] * (p + 1) ** 3 / d["seconds"], "unit": "DOF*RK-stage updates/s",
+            "cores": d["threads"], "kind": "oracle",
+            "sample": f"one residual evaluation (one RK stage) of the {d['E']}-element p={p} shell, "
+                      f"FP64 C oracle, {d['seconds']:.1f} s"}
+
+
 def cpu_baseline(cfg, Q_fn, pr, dt):
     from oracle import oracle as o
     Nz, Nr, p, _, _ = cfg
@@ -385,6 +419,7 @@ def main():
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(cfg, lambda x: inp.shell_state(x, bg, seed), pr, dt)
+            out["cpu_baseline"]["single_core"] = cpu_single_core()
         except Exception as ex:  # report, do not hide
             out["cpu_baseline"] = {"value": None, "error": repr(ex)}
     print(json.dumps(out), flush=True)
