@@ -41,24 +41,30 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
-def alg_bytes(kind, N, E, n_extra=1.2):
+def alg_bytes(kind, N, E, n_extra=1.2, fused=True):
     """Algorithmic HBM bytes of one launch: what the method itself must move,
     each once (state, RK registers, stored geometry), independent of the
-    implementation's intermediate buffers (face traces, partial residuals).
+    implementation's intermediate buffers (face traces, partial residuals,
+    the partial stage output).
 
-    volume:       the state 9N^3, |J| and S^d/|J| at the SPs 10N^3, the
-                  metric S^d at the own-family flux points 9(N+1)N^2 and the
-                  SP positions 3N^3 (gravity), FP64.
-    finish_stage: the extra RK registers the Shu-Osher combination reads
-                  (n_extra on average: 0, 0, 1, 2, 3 over the five stages of
-                  SSPRK(5,3)) and the stage output, 9N^3 each, FP64.
-    stage:        the sum, i.e. 8 [(R_in + 1) 9N^3 + 10N^3 + 9(N+1)N^2 + 3N^3]
-                  per element with R_in = 1 + n_extra.
+    stage:        8 [(R_in + 1) 9N^3 + 10N^3 + 9(N+1)N^2 + 3N^3] per element:
+                  the state 9N^3, the n_extra further RK registers the
+                  Shu-Osher combination reads (0, 0, 1, 2, 3 over the five
+                  stages of SSPRK(5,3): 1.2 on average; R_in = 1 + n_extra)
+                  and the stage output 9N^3, |J| and S^d/|J| at the SPs
+                  10N^3, the metric S^d at the own-family flux points
+                  9(N+1)N^2 and the SP positions 3N^3 (gravity), FP64.
+    volume:       the state and the geometry; in the fused FP64 stage the
+                  volume pass also reads the further registers and writes
+                  the stage output, so all of the stage's bytes.
+    finish_stage: the rest: nothing in the fused FP64 stage (it moves only
+                  intermediate data), else the further registers and the
+                  output, 9N^3 each.
     """
     N2, N3 = N * N, N ** 3
-    vol = 8 * (9 * N3 + 10 * N3 + 9 * (N + 1) * N2 + 3 * N3)
-    fin = 8 * 9 * N3 * (n_extra + 1)
-    per = {"volume": vol, "finish_stage": fin, "stage": vol + fin}.get(kind)
+    geo = 8 * (9 * N3 + 10 * N3 + 9 * (N + 1) * N2 + 3 * N3)
+    rk = 8 * 9 * N3 * (n_extra + 1)
+    per = {"volume": geo + (rk if fused else 0), "finish_stage": 0 if fused else rk, "stage": geo + rk}.get(kind)
     return None if per is None else per * E
 
 

@@ -83,6 +83,9 @@ struct RunDesc {
   double alpha[4];
   int32_t n_in;
   int32_t write_traces;
+  int32_t fuse;        // FP64 stage: k_volume writes sum alpha u + beta dt (R
+                       // without the neighbour viscous half) to `out`, k_finish
+                       // subtracts that half (else k_volume writes Rp)
   double* out;         // stage output
   double beta_dt;
   Phys<double> P;
@@ -124,6 +127,7 @@ struct Run {
   double alpha[4];
   int32_t n_in;
   int32_t write_traces;
+  int32_t fuse;
   GBL double* out;
   double beta_dt;
   Phys<T> P;
@@ -169,6 +173,7 @@ __device__ __forceinline__ void fill_run(Run<T>& r, S& d) {
   }
   r.n_in = d.n_in;
   r.write_traces = d.write_traces;
+  r.fuse = d.fuse;
   r.out = (GBL double*)d.out;
   r.beta_dt = d.beta_dt;
   r.P = cvt_phys<T>(d.P);
@@ -497,6 +502,84 @@ __device__ __forceinline__ void lift_family(int d, int ia0, int ia1, int ia2, co
     const T df = sD[(i * NP + f) * ds];
 #pragma unroll
     for (int v = 0; v < 9; ++v) div[v] += df * sU[(base + f - 1) * 9 + v];
+  }
+}
+
+// E. of k_volume: the lifting of the last family's fluxes, the sources (Eq.
+// "M") and -div/|J| + M at this thread's SP.  Written as the partial residual
+// Rp, or, in a fused FP64 stage (FUSED, K input registers), as the stage
+// output sum_k alpha_k u_k + beta dt (-div/|J| + M) in `out`: the inputs other
+// than the state itself are requested before the lifting, so that they
+// arrive meanwhile, and the state is the SP's own point row.  k_finish then
+// subtracts beta dt times the neighbour half of the viscous flux.
+template <int N, typename T, bool FUSED, int K>
+__device__ __forceinline__ void volume_epilogue(const Run<T>& R, const Phys<T>& P, const T* sR, const T* sD, int ds,
+                                                const T* sU, int tid, int ia0, int ia1, int ia2, T div[9],
+                                                const T xs[3], T ji) {
+  constexpr int N3 = N * N * N;
+  constexpr int RS = row_stride<T>();
+  const int64_t e = R.e;
+  double a[K > 0 ? K : 1][9];
+  if constexpr (FUSED) {
+    if (tid < N3) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (R.in[k] != R.Q) {
+          const GBL double* src = R.in[k] + e * 9 * N3 + tid;
+#pragma unroll
+          for (int v = 0; v < 9; ++v) a[k][v] = src[v * N3];
+        }
+      }
+    }
+  }
+  if (tid < N3) lift_family<N>(2, ia0, ia1, ia2, sD, ds, sU, div);
+  if (tid < N3) {
+    const int sp = tid;
+    T q[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) q[v] = sR[sp * RS + v];
+    T gv[3] = {T(0), T(0), T(0)};
+    if (P.GM != T(0)) {
+      const T r2 = xs[0] * xs[0] + xs[1] * xs[1] + xs[2] * xs[2];
+      const T sc = -P.GM / (r2 * sqrt(r2));
+      gv[0] = sc * xs[0]; gv[1] = sc * xs[1]; gv[2] = sc * xs[2];
+    }
+    const T ir = recip(q[0]);
+    const T* row = sR + sp * RS;
+    const T db = P.powell ? row[24] + row[28] + row[32] : T(0);
+    const T uB = (q[1] * q[5] + q[2] * q[6] + q[3] * q[7]) * ir;
+    T M[9];
+    M[0] = T(0);
+    M[1] = q[0] * gv[0] + T(2) * P.Omega * q[2] - db * q[5];
+    M[2] = q[0] * gv[1] - T(2) * P.Omega * q[1] - db * q[6];
+    M[3] = q[0] * gv[2] - db * q[7];
+    M[4] = q[1] * gv[0] + q[2] * gv[1] + q[3] * gv[2] - db * uB;
+    M[5] = -db * q[1] * ir;
+    M[6] = -db * q[2] * ir;
+    M[7] = -db * q[3] * ir;
+    M[8] = -P.glm_a * q[8];
+    if constexpr (FUSED) {
+      // the state itself: this SP's point row (FP64 here)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (R.in[k] == R.Q) {
+#pragma unroll
+          for (int v = 0; v < 9; ++v) a[k][v] = (double)q[v];
+        }
+      }
+      GBL double* out = R.out + e * 9 * N3 + sp;
+#pragma unroll
+      for (int v = 0; v < 9; ++v) {
+        double x = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) x += R.alpha[k] * a[k][v];
+        out[v * N3] = x + R.beta_dt * (double)(M[v] - div[v] * ji);
+      }
+    } else {
+      GBL T* rp = R.Rp + e * 9 * N3 + sp;
+#pragma unroll
+      for (int v = 0; v < 9; ++v) rp[v * N3] = M[v] - div[v] * ji;
+    }
   }
 }
 
@@ -937,37 +1020,22 @@ void k_volume(Launch L) {
       }
       __syncthreads();
     }
-    if (tid < N3) lift_family<N>(2, ia0, ia1, ia2, sD, ds, sU, div);
-
-    // E. sources (Eq. "M") and the partial residual -div/|J| + M
-    if (tid < N3) {
-      const int sp = tid;
-      T q[9];
-#pragma unroll
-      for (int v = 0; v < 9; ++v) q[v] = sR[sp * RS + v];
-      T gv[3] = {T(0), T(0), T(0)};
-      if (P.GM != T(0)) {
-        const T r2 = xs[0] * xs[0] + xs[1] * xs[1] + xs[2] * xs[2];
-        const T sc = -P.GM / (r2 * sqrt(r2));
-        gv[0] = sc * xs[0]; gv[1] = sc * xs[1]; gv[2] = sc * xs[2];
+    // E. the last family's lifting, then the sources and the partial
+    //    residual; a fused FP64 stage forms its output here (volume_epilogue)
+    if constexpr (sizeof(T) == 8 && !DIAG) {
+      if (R.fuse) {
+        switch (R.n_in) {
+          case 1: volume_epilogue<N, T, true, 1>(R, P, sR, sD, ds, sU, tid, ia0, ia1, ia2, div, xs, ji); break;
+          case 2: volume_epilogue<N, T, true, 2>(R, P, sR, sD, ds, sU, tid, ia0, ia1, ia2, div, xs, ji); break;
+          case 3: volume_epilogue<N, T, true, 3>(R, P, sR, sD, ds, sU, tid, ia0, ia1, ia2, div, xs, ji); break;
+          case 4: volume_epilogue<N, T, true, 4>(R, P, sR, sD, ds, sU, tid, ia0, ia1, ia2, div, xs, ji); break;
+          default: volume_epilogue<N, T, true, 0>(R, P, sR, sD, ds, sU, tid, ia0, ia1, ia2, div, xs, ji); break;
+        }
+      } else {
+        volume_epilogue<N, T, false, 0>(R, P, sR, sD, ds, sU, tid, ia0, ia1, ia2, div, xs, ji);
       }
-      const T ir = recip(q[0]);
-      const T* row = sR + sp * RS;
-      const T db = P.powell ? row[24] + row[28] + row[32] : T(0);
-      const T uB = (q[1] * q[5] + q[2] * q[6] + q[3] * q[7]) * ir;
-      T M[9];
-      M[0] = T(0);
-      M[1] = q[0] * gv[0] + T(2) * P.Omega * q[2] - db * q[5];
-      M[2] = q[0] * gv[1] - T(2) * P.Omega * q[1] - db * q[6];
-      M[3] = q[0] * gv[2] - db * q[7];
-      M[4] = q[1] * gv[0] + q[2] * gv[1] + q[3] * gv[2] - db * uB;
-      M[5] = -db * q[1] * ir;
-      M[6] = -db * q[2] * ir;
-      M[7] = -db * q[3] * ir;
-      M[8] = -P.glm_a * q[8];
-      GBL T* rp = R.Rp + e * 9 * N3 + sp;
-#pragma unroll
-      for (int v = 0; v < 9; ++v) rp[v * N3] = M[v] - div[v] * ji;
+    } else {
+      volume_epilogue<N, T, false, 0>(R, P, sR, sD, ds, sU, tid, ia0, ia1, ia2, div, xs, ji);
     }
     __syncthreads();
   }
@@ -1050,12 +1118,20 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
     if constexpr (GREG) {
       if (tid < 6 * N2) gather_vflux<N>(R, nb6, tid, fv);
     }
-    // this thread's SP: 1/|J|, the partial residual and, for a stage, the
-    // Shu-Osher combination sum_k alpha_k u_k of the registers
+    // this thread's SP: 1/|J|, and either (fused FP64 stage) the stage
+    // output k_volume formed without the neighbour half, or the partial
+    // residual and, for a stage, the Shu-Osher combination sum_k alpha_k u_k
+    // of the registers
     const int sp = tid;
+    const bool fused = STAGE && sizeof(T) == 8 && R.fuse;
     T ji = T(0), rpv[9];  // |J| here; its reciprocal once the loads are issued
     double u[9];
-    if (sp < N3) {
+    if (sp < N3 && fused) {
+      ji = (T)R.detJ[e * N3 + sp];
+      const GBL double* o = R.out + e * 9 * N3 + sp;
+#pragma unroll
+      for (int v = 0; v < 9; ++v) u[v] = o[v * N3];
+    } else if (sp < N3) {
       ji = (T)R.detJ[e * N3 + sp];
       const GBL T* rp = R.Rp + e * 9 * N3 + sp;
 #pragma unroll
@@ -1099,24 +1175,35 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
         for (int c = 0; c < 7; ++c)
           corr[c] += w0 * sV[((2 * d) * 7 + c) * N2 + pq] + wN * sV[((2 * d + 1) * 7 + c) * N2 + pq];
       }
-      double Rv[9];
-#pragma unroll
-      for (int v = 0; v < 9; ++v) {
-        const T c = (v >= 1 && v <= 7) ? corr[v - 1] : T(0);
-        Rv[v] = (double)(rpv[v] - c * ji);
-      }
-      if (!STAGE) {
-        GBL double* Ro = R.R + e * 9 * N3 + sp;
-#pragma unroll
-        for (int v = 0; v < 9; ++v) Ro[v * N3] = Rv[v];
-      } else {
-        // Shu-Osher stage in FP64: sum_k alpha_k u_k + beta dt R
+      if (fused) {
+        // the stage output less beta dt times the neighbour half
         GBL double* out = R.out + e * 9 * N3 + sp;
 #pragma unroll
         for (int v = 0; v < 9; ++v) {
-          const double x = u[v] + R.beta_dt * Rv[v];
+          const double x = (v >= 1 && v <= 7) ? u[v] - R.beta_dt * (double)(corr[v - 1] * ji) : u[v];
           out[v * N3] = x;
           sOut[v * N3 + sp] = x;
+        }
+      } else {
+        double Rv[9];
+#pragma unroll
+        for (int v = 0; v < 9; ++v) {
+          const T c = (v >= 1 && v <= 7) ? corr[v - 1] : T(0);
+          Rv[v] = (double)(rpv[v] - c * ji);
+        }
+        if (!STAGE) {
+          GBL double* Ro = R.R + e * 9 * N3 + sp;
+#pragma unroll
+          for (int v = 0; v < 9; ++v) Ro[v * N3] = Rv[v];
+        } else {
+          // Shu-Osher stage in FP64: sum_k alpha_k u_k + beta dt R
+          GBL double* out = R.out + e * 9 * N3 + sp;
+#pragma unroll
+          for (int v = 0; v < 9; ++v) {
+            const double x = u[v] + R.beta_dt * Rv[v];
+            out[v * N3] = x;
+            sOut[v * N3 + sp] = x;
+          }
         }
       }
     }
@@ -1807,6 +1894,7 @@ sdm_status stage_parts(sdm_ctx* c, const sdm_params* p, double* const* regs, int
   r.out = regs[stg->out];
   r.beta_dt = stg->beta * dt;
   r.write_traces = 1;
+  r.fuse = c->arith == 0 ? 1 : 0;  // FP64: k_volume forms the stage output
   Launch L = single(r);
   if (parts == 3 && c->order) {
     // overlapped schedule: volume passes chunk by chunk on the caller's
@@ -1954,6 +2042,7 @@ sdm_status sdm_batch_stage(const sdm_batch_item* items, int n_items, void* batch
     r.out = it.regs[st.out];
     r.beta_dt = st.beta * it.dt;
     r.write_traces = 1;
+    r.fuse = c->arith == 0 ? 1 : 0;
     all.push_back(r);
     pre_all.push_back(pre_all.back() + r.E);
     if (!st.traces_valid) {
