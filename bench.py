@@ -374,6 +374,7 @@ def main():
                  "avg_launch_ms": avg_ms, "alg_bytes_per_launch": bytes_launch,
                  "alg_fp64_flops_per_launch": flops_launch, "alg_hbm_gbs": hbm_gbs,
                  "alg_hbm_frac": hbm_gbs / HBM_PEAK_GBS if hbm_gbs else None,
+                 "alg_fp64_tflops": tflops, "alg_fp64_frac": tflops / FP64_PEAK_TFLOPS,
                  "measured_hbm_gbs": traffic / t / 1e9 if traffic else None})
     # the whole stage (all kernels of one RK stage) against the same bounds
     t_stage = ms * 1e-3 / stages
