@@ -11,11 +11,14 @@
 //             of Q and grad Q to each flux-point family, total flux at the
 //             interior flux points, Rusanov + own half of the BR1 viscous flux
 //             at the face points (wall / Dirichlet fluxes complete), flux
-//             divergence, sources -> partial residual; writes this side's
-//             viscous normal flux for the neighbour
-//   k_finish  adds the neighbour half of the BR1 viscous flux, then either
-//             stores R or applies the Shu-Osher stage update in FP64, and
-//             writes the new state's face traces for the next stage.
+//             divergence, sources -> partial residual (without the neighbour
+//             half of the viscous flux), or, in an FP64 stage, the Shu-Osher
+//             combination with it written to the output register; writes
+//             this side's viscous normal flux for the neighbour
+//   k_finish  adds the neighbour half of the BR1 viscous flux: stores R, or
+//             corrects the FP64 stage output in place, or (FP32-mixed) applies
+//             the Shu-Osher update in FP64; in a stage it writes the new
+//             state's face traces for the next stage.
 // The face coupling uses the per-element neighbour/orientation table; each
 // interior face is evaluated by both of its elements, with the symmetric face
 // normal n = (S_own - S_other)/2 so the two values are exact negatives.
