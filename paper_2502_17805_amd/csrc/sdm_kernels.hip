@@ -1179,12 +1179,13 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
           corr[c] += w0 * sV[((2 * d) * 7 + c) * N2 + pq] + wN * sV[((2 * d + 1) * 7 + c) * N2 + pq];
       }
       if (fused) {
-        // the stage output less beta dt times the neighbour half
+        // the stage output less beta dt times the neighbour half; rho and psi
+        // (no viscous flux) are final as k_volume wrote them
         GBL double* out = R.out + e * 9 * N3 + sp;
 #pragma unroll
         for (int v = 0; v < 9; ++v) {
           const double x = (v >= 1 && v <= 7) ? u[v] - R.beta_dt * (double)(corr[v - 1] * ji) : u[v];
-          out[v * N3] = x;
+          if (v >= 1 && v <= 7) out[v * N3] = x;
           sOut[v * N3 + sp] = x;
         }
       } else {
