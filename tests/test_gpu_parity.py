@@ -227,3 +227,39 @@ def test_residual_and_stage_solar_benchmark(sd, oracle):
     want = Q + beta * dt * Ro
     scale = np.abs(Q).max(axis=(0, 2)) + dt * ts
     assert (np.abs(got - want).max(axis=(0, 2)) <= TOL * scale).all()
+
+
+@pytest.mark.parametrize("arith", [0, 1])
+def test_generic_stage_forms(sd, oracle, arith):
+    """Shu-Osher stages other than SSPRK(5,3)'s: no inputs, inputs that do
+    not include the state, and four inputs with the state among them written
+    in place.  Each equals sum alpha u + beta dt R(cur) with R from the
+    library's residual (the unfused path, itself checked against the oracle),
+    to round-off of the term scale (FP64: the fused stage; FP32-mixed: the
+    split one)."""
+    import torch
+    ml, mo, bg, Q, pr = _c1(sd, oracle)
+    pg = sd.make_params(**pr)
+    rng = np.random.default_rng(11)
+    regs0 = [Q * (1.0 + 1e-3 * rng.standard_normal(Q.shape)) for _ in range(4)]
+    dt = 0.01
+    _, ts = mo.residual(oracle.make_params(**pr), regs0[1], with_scale=True)
+    tol = TOL if arith == 0 else 2e-6
+    for cur, inputs, beta, out in [(1, [], 0.4, 2),
+                                   (1, [(0, 0.3), (3, 0.7)], 0.25, 2),
+                                   (1, [(0, 0.1), (2, 0.2), (1, 0.6), (3, 0.1)], 0.3, 1)]:
+        s = sd.Solver(ml, arith=arith)
+        for r in range(4):
+            s.regs[r].copy_(torch.from_numpy(regs0[r]))
+        R = s.residual(pg, s.regs[cur].clone()).cpu().numpy()
+        s._traces_of = None
+        s.stage(pg, cur, inputs, beta, out, dt)
+        got = s.regs[out].cpu().numpy()
+        want = sum(al * regs0[k] for k, al in inputs) + beta * dt * R if inputs else beta * dt * R
+        scale = max(np.abs(regs0).max(), 1e-300) + dt * ts
+        err = np.abs(got - want).max(axis=(0, 2))
+        assert (err <= tol * scale).all(), (cur, inputs, out, err / scale)
+        # registers that are not the output are untouched
+        for r in range(4):
+            if r != out:
+                assert np.array_equal(s.regs[r].cpu().numpy(), regs0[r]), r
