@@ -54,10 +54,11 @@ def alg_bytes(kind, N, E, n_extra=1.2, fused=True):
                   and the stage output 9N^3, |J| and S^d/|J| at the SPs
                   10N^3, the metric S^d at the own-family flux points
                   9(N+1)N^2 and the SP positions 3N^3 (gravity), FP64.
-    volume:       the state and the geometry; in the fused FP64 stage the
-                  volume pass also reads the further registers and writes
-                  the stage output, so all of the stage's bytes.
-    finish_stage: the rest: nothing in the fused FP64 stage (it moves only
+    volume:       the state and the geometry; with the fused stage (both
+                  arithmetics) the volume pass also reads the further
+                  registers and writes the stage output, so all of the
+                  stage's bytes.
+    finish_stage: the rest: nothing with the fused stage (it moves only
                   intermediate data), else the further registers and the
                   output, 9N^3 each.
     """

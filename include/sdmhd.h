@@ -216,13 +216,10 @@ sdm_status sdm_rk_stage(sdm_ctx* ctx, const sdm_params* prm, double* const* regs
  * reads import_q and leaves this partition's viscous face fluxes in `ws`,
  * see sdm_workspace_traces) and the finish half (the neighbour half, read
  * from import_v on import faces, and the Shu-Osher update; it leaves the
- * new state's face traces in `ws`).  In FP64 the volume half already forms
- * the Shu-Osher combination with that partial residual and writes it to
- * regs[out] (the inputs equal to regs[cur] are taken from the element data
- * it holds), and the finish half subtracts beta dt times the neighbour half
- * in place; in FP32-mixed the partial residual goes to `ws` and the finish
- * half forms the combination.  Between the halves regs[out] is therefore
- * not a state.  A split run exchanges the Q traces
+ * new state's face traces in `ws`).  The volume half already forms the
+ * Shu-Osher combination (FP64) with that partial residual and writes it to
+ * regs[out], and the finish half subtracts beta dt times the neighbour half
+ * in place.  Between the halves regs[out] is therefore not a state.  A split run exchanges the Q traces
  * before the volume half and the viscous fluxes between the halves.  Same
  * arguments as sdm_rk_stage; volume followed by finish equals sdm_rk_stage
  * bitwise. */

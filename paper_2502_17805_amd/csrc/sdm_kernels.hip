@@ -12,13 +12,12 @@
 //             interior flux points, Rusanov + own half of the BR1 viscous flux
 //             at the face points (wall / Dirichlet fluxes complete), flux
 //             divergence, sources -> partial residual (without the neighbour
-//             half of the viscous flux), or, in an FP64 stage, the Shu-Osher
+//             half of the viscous flux), or, in a stage, the FP64 Shu-Osher
 //             combination with it written to the output register; writes
 //             this side's viscous normal flux for the neighbour
 //   k_finish  adds the neighbour half of the BR1 viscous flux: stores R, or
-//             corrects the FP64 stage output in place, or (FP32-mixed) applies
-//             the Shu-Osher update in FP64; in a stage it writes the new
-//             state's face traces for the next stage.
+//             corrects the stage output in place; in a stage it writes the
+//             new state's face traces for the next stage.
 // The face coupling uses the per-element neighbour/orientation table; each
 // interior face is evaluated by both of its elements, with the symmetric face
 // normal n = (S_own - S_other)/2 so the two values are exact negatives.
@@ -86,9 +85,10 @@ struct RunDesc {
   double alpha[4];
   int32_t n_in;
   int32_t write_traces;
-  int32_t fuse;        // FP64 stage: k_volume writes sum alpha u + beta dt (R
-                       // without the neighbour viscous half) to `out`, k_finish
-                       // subtracts that half (else k_volume writes Rp)
+  int32_t fuse;        // stage: k_volume writes sum alpha u + beta dt (R
+                       // without the neighbour viscous half) to `out` and
+                       // k_finish subtracts that half; residual: k_volume
+                       // writes Rp, k_finish adds the half and writes R
   double* out;         // stage output
   double beta_dt;
   Phys<double> P;
@@ -510,11 +510,12 @@ __device__ __forceinline__ void lift_family(int d, int ia0, int ia1, int ia2, co
 
 // E. of k_volume: the lifting of the last family's fluxes, the sources (Eq.
 // "M") and -div/|J| + M at this thread's SP.  Written as the partial residual
-// Rp, or, in a fused FP64 stage (FUSED, K input registers), as the stage
-// output sum_k alpha_k u_k + beta dt (-div/|J| + M) in `out`: the inputs other
-// than the state itself are requested before the lifting, so that they
-// arrive meanwhile, and the state is the SP's own point row.  k_finish then
-// subtracts beta dt times the neighbour half of the viscous flux.
+// Rp (residual mode), or, in a stage (FUSED, K input registers), as the stage
+// output sum_k alpha_k u_k + beta dt (-div/|J| + M) in `out`, in FP64: the
+// input registers are requested before the lifting, so that they arrive
+// meanwhile, except, in FP64, the state itself, which is the SP's own point
+// row (in FP32-mixed the row holds it in FP32).  k_finish then subtracts
+// beta dt times the neighbour half of the viscous flux.
 template <int N, typename T, bool FUSED, int K>
 __device__ __forceinline__ void volume_epilogue(const Run<T>& R, const Phys<T>& P, const T* sR, const T* sD, int ds,
                                                 const T* sU, int tid, int ia0, int ia1, int ia2, T div[9],
@@ -527,7 +528,7 @@ __device__ __forceinline__ void volume_epilogue(const Run<T>& R, const Phys<T>& 
     if (tid < N3) {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (R.in[k] != R.Q) {
+        if (sizeof(T) != 8 || R.in[k] != R.Q) {
           const GBL double* src = R.in[k] + e * 9 * N3 + tid;
 #pragma unroll
           for (int v = 0; v < 9; ++v) a[k][v] = src[v * N3];
@@ -565,7 +566,7 @@ __device__ __forceinline__ void volume_epilogue(const Run<T>& R, const Phys<T>& 
       // the state itself: this SP's point row (FP64 here)
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (R.in[k] == R.Q) {
+        if (sizeof(T) == 8 && R.in[k] == R.Q) {
 #pragma unroll
           for (int v = 0; v < 9; ++v) a[k][v] = (double)q[v];
         }
@@ -1024,8 +1025,8 @@ void k_volume(Launch L) {
       __syncthreads();
     }
     // E. the last family's lifting, then the sources and the partial
-    //    residual; a fused FP64 stage forms its output here (volume_epilogue)
-    if constexpr (sizeof(T) == 8 && !DIAG) {
+    //    residual; a stage forms its output here (volume_epilogue)
+    if constexpr (!DIAG) {
       if (R.fuse) {
         switch (R.n_in) {
           case 1: volume_epilogue<N, T, true, 1>(R, P, sR, sD, ds, sU, tid, ia0, ia1, ia2, div, xs, ji); break;
@@ -1073,27 +1074,6 @@ __device__ __forceinline__ void gather_vflux(const Run<T>& R, const GBL int32_t*
   }
 }
 
-// sum_k alpha_k u_k at solution point sp of element e over the stage's K
-// input registers, all K x 9 loads issued before the sums (FP64)
-template <int N, int K, typename T>
-__device__ __forceinline__ void rk_combine(const Run<T>& R, int64_t e, int sp, double u[9]) {
-  constexpr int N3 = N * N * N;
-  double a[K > 0 ? K : 1][9];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const GBL double* src = R.in[k] + e * 9 * N3 + sp;
-#pragma unroll
-    for (int v = 0; v < 9; ++v) a[k][v] = src[v * N3];
-  }
-#pragma unroll
-  for (int v = 0; v < 9; ++v) {
-    double x = 0.0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) x += R.alpha[k] * a[k][v];
-    u[v] = x;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // k_finish: neighbour half of the viscous common flux, then R or the stage
 // ---------------------------------------------------------------------------
@@ -1121,34 +1101,21 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
     if constexpr (GREG) {
       if (tid < 6 * N2) gather_vflux<N>(R, nb6, tid, fv);
     }
-    // this thread's SP: 1/|J|, and either (fused FP64 stage) the stage
-    // output k_volume formed without the neighbour half, or the partial
-    // residual and, for a stage, the Shu-Osher combination sum_k alpha_k u_k
-    // of the registers
+    // this thread's SP: 1/|J|, and either (stage) the stage output k_volume
+    // formed without the neighbour half, or (residual) the partial residual
     const int sp = tid;
-    const bool fused = STAGE && sizeof(T) == 8 && R.fuse;
     T ji = T(0), rpv[9];  // |J| here; its reciprocal once the loads are issued
     double u[9];
-    if (sp < N3 && fused) {
+    if (sp < N3) {
       ji = (T)R.detJ[e * N3 + sp];
-      const GBL double* o = R.out + e * 9 * N3 + sp;
+      if constexpr (STAGE) {
+        const GBL double* o = R.out + e * 9 * N3 + sp;
 #pragma unroll
-      for (int v = 0; v < 9; ++v) u[v] = o[v * N3];
-    } else if (sp < N3) {
-      ji = (T)R.detJ[e * N3 + sp];
-      const GBL T* rp = R.Rp + e * 9 * N3 + sp;
+        for (int v = 0; v < 9; ++v) u[v] = o[v * N3];
+      } else {
+        const GBL T* rp = R.Rp + e * 9 * N3 + sp;
 #pragma unroll
-      for (int v = 0; v < 9; ++v) rpv[v] = rp[v * N3];
-      if (STAGE) {
-        // every input register's loads issued before any is combined (one
-        // straight-line body per input count)
-        switch (R.n_in) {
-          case 1: rk_combine<N, 1>(R, e, sp, u); break;
-          case 2: rk_combine<N, 2>(R, e, sp, u); break;
-          case 3: rk_combine<N, 3>(R, e, sp, u); break;
-          case 4: rk_combine<N, 4>(R, e, sp, u); break;
-          default: rk_combine<N, 0>(R, e, sp, u); break;
-        }
+        for (int v = 0; v < 9; ++v) rpv[v] = rp[v * N3];
       }
     }
     if constexpr (GREG) {
@@ -1178,7 +1145,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
         for (int c = 0; c < 7; ++c)
           corr[c] += w0 * sV[((2 * d) * 7 + c) * N2 + pq] + wN * sV[((2 * d + 1) * 7 + c) * N2 + pq];
       }
-      if (fused) {
+      if constexpr (STAGE) {
         // the stage output less beta dt times the neighbour half; rho and psi
         // (no viscous flux) are final as k_volume wrote them
         GBL double* out = R.out + e * 9 * N3 + sp;
@@ -1189,25 +1156,11 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
           sOut[v * N3 + sp] = x;
         }
       } else {
-        double Rv[9];
+        GBL double* Ro = R.R + e * 9 * N3 + sp;
 #pragma unroll
         for (int v = 0; v < 9; ++v) {
           const T c = (v >= 1 && v <= 7) ? corr[v - 1] : T(0);
-          Rv[v] = (double)(rpv[v] - c * ji);
-        }
-        if (!STAGE) {
-          GBL double* Ro = R.R + e * 9 * N3 + sp;
-#pragma unroll
-          for (int v = 0; v < 9; ++v) Ro[v * N3] = Rv[v];
-        } else {
-          // Shu-Osher stage in FP64: sum_k alpha_k u_k + beta dt R
-          GBL double* out = R.out + e * 9 * N3 + sp;
-#pragma unroll
-          for (int v = 0; v < 9; ++v) {
-            const double x = u[v] + R.beta_dt * Rv[v];
-            out[v * N3] = x;
-            sOut[v * N3 + sp] = x;
-          }
+          Ro[v * N3] = (double)(rpv[v] - c * ji);
         }
       }
     }
@@ -1898,7 +1851,7 @@ sdm_status stage_parts(sdm_ctx* c, const sdm_params* p, double* const* regs, int
   r.out = regs[stg->out];
   r.beta_dt = stg->beta * dt;
   r.write_traces = 1;
-  r.fuse = c->arith == 0 ? 1 : 0;  // FP64: k_volume forms the stage output
+  r.fuse = 1;  // k_volume forms the stage output
   Launch L = single(r);
   if (parts == 3 && c->order) {
     // overlapped schedule: volume passes chunk by chunk on the caller's
@@ -2046,7 +1999,7 @@ sdm_status sdm_batch_stage(const sdm_batch_item* items, int n_items, void* batch
     r.out = it.regs[st.out];
     r.beta_dt = st.beta * it.dt;
     r.write_traces = 1;
-    r.fuse = c->arith == 0 ? 1 : 0;
+    r.fuse = 1;
     all.push_back(r);
     pre_all.push_back(pre_all.back() + r.E);
     if (!st.traces_valid) {
