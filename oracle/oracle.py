@@ -64,40 +64,73 @@ def make_params(**kw) -> Params:
 _lib = None
 
 
+def _configure(L):
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_int
+    L.or_shell_new.restype = vp
+    L.or_shell_new.argtypes = [ip, ip, ip, C.c_double, C.c_double]
+    L.or_box_new.restype = vp
+    L.or_box_new.argtypes = [ip, ip, ip, ip, C.c_double, C.c_double, C.c_double, ip, C.c_double]
+    L.or_mesh_free.argtypes = [vp]
+    L.or_mesh_sizes.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.or_mesh_get.argtypes = [vp, C.c_char_p, vp]
+    L.or_mesh_get.restype = ip
+    L.or_residual.argtypes = [vp, C.POINTER(Params), vp, vp, vp, vp, vp]
+    L.or_residual.restype = ip
+    L.or_ssprk53_step.argtypes = [vp, C.POINTER(Params), vp, vp, C.c_double]
+    L.or_ssprk53_step.restype = ip
+    L.or_ssprk53_table.argtypes = [vp, vp, vp]
+    L.or_diagnostics.argtypes = [vp, C.POINTER(Params), vp, vp, vp]
+    L.or_diagnostics.restype = ip
+    L.or_sph_profiles.argtypes = [vp, vp, C.c_double, C.c_double, ip, ip, vp]
+    L.or_sph_profiles.restype = ip
+    L.or_tables.argtypes = [ip, vp, vp, vp, vp, vp]
+    L.or_tables.restype = ip
+    L.or_threads.restype = ip
+    L.or_point_flux.argtypes = [vp, vp, C.c_double, vp, C.POINTER(Params), vp, vp]
+    L.or_point_rusanov.argtypes = [vp, vp, vp, C.POINTER(Params), vp]
+    L.or_point_cf.argtypes = [vp, vp, C.POINTER(Params)]
+    L.or_point_cf.restype = C.c_double
+    L.or_point_wall_flux.argtypes = [vp, vp, C.c_double, vp, ip, C.POINTER(Params), vp]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_SO):
             build()
-        L = C.CDLL(_SO)
-        vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_int
-        L.or_shell_new.restype = vp
-        L.or_shell_new.argtypes = [ip, ip, ip, C.c_double, C.c_double]
-        L.or_box_new.restype = vp
-        L.or_box_new.argtypes = [ip, ip, ip, ip, C.c_double, C.c_double, C.c_double, ip, C.c_double]
-        L.or_mesh_free.argtypes = [vp]
-        L.or_mesh_sizes.argtypes = [vp, C.POINTER(C.c_int64)]
-        L.or_mesh_get.argtypes = [vp, C.c_char_p, vp]
-        L.or_mesh_get.restype = ip
-        L.or_residual.argtypes = [vp, C.POINTER(Params), vp, vp, vp, vp, vp]
-        L.or_residual.restype = ip
-        L.or_ssprk53_step.argtypes = [vp, C.POINTER(Params), vp, vp, C.c_double]
-        L.or_ssprk53_step.restype = ip
-        L.or_ssprk53_table.argtypes = [vp, vp, vp]
-        L.or_diagnostics.argtypes = [vp, C.POINTER(Params), vp, vp, vp]
-        L.or_diagnostics.restype = ip
-        L.or_sph_profiles.argtypes = [vp, vp, C.c_double, C.c_double, ip, ip, vp]
-        L.or_sph_profiles.restype = ip
-        L.or_tables.argtypes = [ip, vp, vp, vp, vp, vp]
-        L.or_tables.restype = ip
-        L.or_threads.restype = ip
-        L.or_point_flux.argtypes = [vp, vp, C.c_double, vp, C.POINTER(Params), vp, vp]
-        L.or_point_rusanov.argtypes = [vp, vp, vp, C.POINTER(Params), vp]
-        L.or_point_cf.argtypes = [vp, vp, C.POINTER(Params)]
-        L.or_point_cf.restype = C.c_double
-        L.or_point_wall_flux.argtypes = [vp, vp, C.c_double, vp, ip, C.POINTER(Params), vp]
-        _lib = L
+        _lib = _configure(C.CDLL(_SO))
     return _lib
+
+
+def build_variant(source_text: str, path: str) -> str:
+    """Compile a modified copy of the oracle source into `path` (the tests use
+    it to plant a mistake and check that a pin catches it)."""
+    src = path + ".c"
+    with open(src, "w") as f:
+        f.write(source_text)
+    subprocess.run(["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                    "-fPIC", "-shared", "-I", _HERE, "-o", path, src, "-lm"], check=True)
+    return path
+
+
+def source_text() -> str:
+    with open(_SRC) as f:
+        return f.read()
+
+
+def swap_library(path):
+    """Make every call of this module use the library at `path` (None: the
+    built oracle); returns the previous library object for swap_back."""
+    global _lib
+    prev = _lib
+    _lib = None if path is None else _configure(C.CDLL(path))
+    return prev
+
+
+def swap_back(prev):
+    global _lib
+    _lib = prev
 
 
 def _ptr(a):
@@ -157,8 +190,9 @@ class Mesh:
         if not handle:
             raise ValueError("mesh construction failed")
         self._h = handle
+        self._L = lib()  # the library that made the handle serves every call on it
         s = (C.c_int64 * 4)()
-        lib().or_mesh_sizes(handle, s)
+        self._L.or_mesh_sizes(handle, s)
         self.E, self.F, self.NB, self.N = int(s[0]), int(s[1]), int(s[2]), int(s[3])
 
     @classmethod
@@ -172,7 +206,7 @@ class Mesh:
     def __del__(self):
         try:
             if self._h:
-                lib().or_mesh_free(self._h)
+                self._L.or_mesh_free(self._h)
                 self._h = None
         except Exception:
             pass
@@ -186,7 +220,7 @@ class Mesh:
                   "W3detJ": ((E, N3), np.float64), "x_bfp": ((self.NB, 3, N * N), np.float64)}
         shp, dt = shapes[name]
         out = np.zeros(shp, dtype=dt)
-        if lib().or_mesh_get(self._h, name.encode(), _ptr(out)):
+        if self._L.or_mesh_get(self._h, name.encode(), _ptr(out)):
             raise KeyError(name)
         return out
 
@@ -196,7 +230,7 @@ class Mesh:
         ts = np.zeros(9)
         dB = np.zeros((self.E, self.N ** 3)) if with_divB else None
         g = None if ghost is None else np.ascontiguousarray(ghost, dtype=np.float64)
-        rc = lib().or_residual(self._h, C.byref(prm), _ptr(Q), _ptr(g), _ptr(R), _ptr(ts), _ptr(dB))
+        rc = self._L.or_residual(self._h, C.byref(prm), _ptr(Q), _ptr(g), _ptr(R), _ptr(ts), _ptr(dB))
         if rc:
             raise RuntimeError("oracle residual failed (Dirichlet face without ghost data)")
         out = [R]
@@ -209,7 +243,7 @@ class Mesh:
     def step(self, prm, Q, dt, ghost=None):
         Q = np.array(Q, dtype=np.float64, copy=True, order="C")
         g = None if ghost is None else np.ascontiguousarray(ghost, dtype=np.float64)
-        if lib().or_ssprk53_step(self._h, C.byref(prm), _ptr(Q), _ptr(g), float(dt)):
+        if self._L.or_ssprk53_step(self._h, C.byref(prm), _ptr(Q), _ptr(g), float(dt)):
             raise RuntimeError("oracle step failed")
         return Q
 
@@ -218,7 +252,7 @@ class Mesh:
         w B_phi^2/2 over the SPs in the bin, shape (n_r, n_th, 5)."""
         Q = np.ascontiguousarray(Q, dtype=np.float64)
         out = np.zeros((n_r, n_th, 5))
-        if lib().or_sph_profiles(self._h, _ptr(Q), float(rb), float(rt), int(n_r), int(n_th), _ptr(out)):
+        if self._L.or_sph_profiles(self._h, _ptr(Q), float(rb), float(rt), int(n_r), int(n_th), _ptr(out)):
             raise ValueError("bad bin counts or radii")
         return out
 
@@ -226,6 +260,6 @@ class Mesh:
         Q = np.ascontiguousarray(Q, dtype=np.float64)
         out = np.zeros(16)
         g = None if ghost is None else np.ascontiguousarray(ghost, dtype=np.float64)
-        if lib().or_diagnostics(self._h, C.byref(prm), _ptr(Q), _ptr(g), _ptr(out)):
+        if self._L.or_diagnostics(self._h, C.byref(prm), _ptr(Q), _ptr(g), _ptr(out)):
             raise RuntimeError("oracle diagnostics failed")
         return out

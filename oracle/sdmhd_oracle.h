@@ -28,7 +28,15 @@
  *                       wave convergence at order p, viscous and resistive
  *                       decay rates, GLM divergence wave, spherical
  *                       symmetry, rotation equivariance, hydrostatic
- *                       convergence
+ *                       convergence; the sources and the radiative flux by
+ *                       closed forms: Coriolis turning of a uniform flow
+ *                       and its inertial oscillation, the exact residual of
+ *                       a linear divergent B with and without the Powell
+ *                       terms, div(kappa_r rho C_p grad T) for quadratic T
+ *                       with constant and radius-squared kappa_r (exact) and
+ *                       radius-linear kappa_r on the shell (order p - 1);
+ *                       planted sign and factor mistakes in those terms
+ *                       fail these pins
  *   or_ssprk53_*        order conditions, SSP coefficient, third-order
  *                       convergence, table = independent derivation
  *   or_diagnostics      exact integrals of uniform and polynomial states,
