@@ -139,30 +139,25 @@ def _timed_steps(torch, s, prm, dt, steps):
     return ev0.elapsed_time(ev1), time.perf_counter() - t0
 
 
-def run_gpu(sd, inp, cfg_name, arith, steps, warmup, mesh, Q, pr, dt, overlap, prof_steps=5):
-    """Timed steps with the overlapped schedule (overlap = its minimum chunk
-    size, 0 = off), the same number of plain-schedule steps, then a few
-    plain steps with the library's per-launch HIP events (per-kernel times)."""
+def run_gpu(sd, inp, cfg_name, arith, steps, warmup, mesh, Q, pr, dt, prof_steps=5):
+    """Timed steps, then a few steps with the library's per-launch HIP events
+    (per-kernel times)."""
     import torch
     s = sd.Solver(mesh, arith=arith)
     prm = sd.make_params(**pr)
     s.set_state(torch.from_numpy(Q))
-    chunks = s.set_overlap(overlap)
     for _ in range(warmup):
         s.step(prm, dt)
     ms, wall = _timed_steps(torch, s, prm, dt, steps)
-    s.set_overlap(0)
-    ms_plain, _ = _timed_steps(torch, s, prm, dt, steps) if chunks else (ms, wall)
     s.profile(True)
     _timed_steps(torch, s, prm, dt, prof_steps)
     prof = s.profile_read()
     s.profile(False)
     d = s.diagnostics(prm)
-    return {"ms": ms, "wall": wall, "chunks": chunks, "ms_plain": ms_plain, "prof": prof,
-            "prof_steps": prof_steps, "diag": d}
+    return {"ms": ms, "wall": wall, "prof": prof, "prof_steps": prof_steps, "diag": d}
 
 
-def run_shard(sd, mesh, Q, pr, dt, steps, warmup, overlap):
+def run_shard(sd, mesh, Q, pr, dt, steps, warmup):
     """One GPU's share of the shell split by cube patch (6 ways): patch 0 with
     its partition faces as import faces.  The halo buffers are filled once
     from an unsplit residual evaluation (a split run would refresh them
@@ -177,14 +172,13 @@ def run_shard(sd, mesh, Q, pr, dt, steps, warmup, overlap):
     s = sd.Solver(sh.mesh)
     prm = sd.make_params(import_q=iq, import_v=iv, **pr)
     s.set_state(torch.from_numpy(Q[sh.elems]))
-    chunks = s.set_overlap(overlap)
     for _ in range(warmup):
         s.step(prm, dt)
     ms = _timed_steps(torch, s, prm, dt, steps)[0] / steps
     dof = sh.mesh.E * sh.mesh.N ** 3
     return {"workload": f"cube patch 0 of the same shell ({sh.mesh.E} elements, {len(sh.imports)} import faces), "
                         "FP64, halo buffers fixed", "elements": sh.mesh.E, "ms_per_step": ms,
-            "value": dof * 5 / (ms * 1e-3), "unit": "DOF*RK-stage updates/s", "overlap_chunks": chunks}
+            "value": dof * 5 / (ms * 1e-3), "unit": "DOF*RK-stage updates/s"}
 
 
 def run_serving(n_requests, ariths):
@@ -276,7 +270,7 @@ def cpu_baseline(cfg, Q_fn, pr, dt):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="shell_55296_p5", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -285,10 +279,6 @@ def main():
     ap.add_argument("--cfl", type=float, default=0.1)
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="served-ensemble leg: that many Poisson-arriving runs of 500 steps (0: skip)")
-    ap.add_argument("--overlap", type=int, default=0, metavar="MIN_CHUNK",
-                    help="time the overlapped stage schedule (element chunks of at least MIN_CHUNK elements, "
-                         "whole radial layers) beside the plain one; 0 = plain schedule only (the default: "
-                         "on the 55,296-element shell the overlapped schedule measured 9 %% slower)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="BYTES",
                     help="first run a plain device copy of BYTES bytes (read BYTES, write BYTES) three "
                          "times, the reference that HBM byte counters are scaled by")
@@ -339,20 +329,17 @@ def main():
 
     res = {}
     for arith in ((0,) if args.no_mixed else (0, 1)):
-        r = run_gpu(sd, inp, args.config, arith, args.steps, args.warmup, mesh, Q, pr, dt, args.overlap)
+        r = run_gpu(sd, inp, args.config, arith, args.steps, args.warmup, mesh, Q, pr, dt)
         res[arith] = r
-        print(f"# arith={arith}: {r['ms'] / args.steps:.3f} ms/step ({r['chunks']} chunks), plain "
-              f"{r['ms_plain'] / args.steps:.3f}; kernels {r['prof']}; KE={r['diag'][3]:.3e} "
-              f"nan={r['diag'][8]}", file=sys.stderr, flush=True)
+        print(f"# arith={arith}: {r['ms'] / args.steps:.3f} ms/step; kernels {r['prof']}; "
+              f"KE={r['diag'][3]:.3e} nan={r['diag'][8]}", file=sys.stderr, flush=True)
 
     r0 = res[0]
     ms, prof, diag = r0["ms"], r0["prof"], r0["diag"]
     stages = 5 * args.steps
     value = dof * stages / (ms * 1e-3)
     # roofline of the dominant kernel (largest summed time), from the HIP
-    # events the library records around each launch on its stream, in
-    # plain-schedule steps (in the overlapped schedule the two passes share
-    # the GPU, so a launch's duration is not its own).  Its bound is the
+    # events the library records around each launch on its stream.  Its bound is the
     # larger of the two algorithmic times: bytes at the HBM peak, FP64 flops
     # at the FP64 vector peak (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4
     # GHz = 78.6 TFLOP/s).
@@ -410,10 +397,7 @@ def main():
                    "elements": mesh.E, "p": p, "dof": dof, "stages_per_step": 5, "parallelism": "single GPU"},
         "roofline": roof,
         "stage_roofline": stage_roof,
-        "schedule": {"overlap_min_chunk": args.overlap, "chunks": r0["chunks"],
-                     "plain_ms_per_step": r0["ms_plain"] / args.steps,
-                     "plain_value": dof * stages / (r0["ms_plain"] * 1e-3)},
-        "kernels_ms_per_step_plain": {k: v[0] / r0["prof_steps"] for k, v in prof.items()},
+        "kernels_ms_per_step": {k: v[0] / r0["prof_steps"] for k, v in prof.items()},
         "variable_dof_value": 9 * value,
         "variable_dof_unit": "variable-DOF*RK-stage updates/s (9 variables per solution point)",
     }
@@ -421,9 +405,8 @@ def main():
         r1 = res[1]
         ms1 = r1["ms"]
         out["mixed_fp32"] = {"value": dof * stages / (ms1 * 1e-3), "ms_per_step": ms1 / args.steps,
-                             "plain_ms_per_step": r1["ms_plain"] / args.steps,
-                             "kernels_ms_per_step_plain": {k: v[0] / r1["prof_steps"]
-                                                           for k, v in r1["prof"].items()},
+                             "kernels_ms_per_step": {k: v[0] / r1["prof_steps"]
+                                                     for k, v in r1["prof"].items()},
                              "speedup_vs_fp64": ms / ms1}
     if args.serve_requests > 0:
         out["serving"] = run_serving(args.serve_requests, (0,) if args.no_mixed else (0, 1))
@@ -431,7 +414,7 @@ def main():
             print(f"# serving {k}: p50 {v['p50_latency_s']:.2f} s, p99 {v['p99_latency_s']:.2f} s, "
                   f"{v['dof_stage_per_s']:.3e} DOF-stage/s", file=sys.stderr, flush=True)
     if not args.no_shard and args.config != "shell_48_p5":
-        out["shard_6way"] = run_shard(sd, mesh, Q, pr, dt, args.steps, args.warmup, args.overlap)
+        out["shard_6way"] = run_shard(sd, mesh, Q, pr, dt, min(args.steps, 20), args.warmup)
         print(f"# shard: {out['shard_6way']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         try:

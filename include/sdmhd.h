@@ -10,9 +10,7 @@
  * named there.  Device work is hand-written HIP; every pointer marked
  * "device" must be device memory of the context's GPU, allocated and owned
  * by the caller (the library never frees it and allocates no device memory
- * except its static constant tables and, with the overlapped stage schedule
- * of sdm_set_overlap, a 4-byte-per-element order table and a second stream
- * per context).  Calls that take a stream only enqueue
+ * except its static constant tables).  Calls that take a stream only enqueue
  * work on it; results are valid after the stream is synchronised.
  *
  * Layouts (all row-major, last index fastest):
@@ -126,14 +124,26 @@ sdm_status sdm_tables(int p, double* xs, double* xf, double* I, double* D, doubl
 
 /* ---------------- device context ------------------------------------- */
 
-/* arith: 0 = FP64 throughout; 1 = mixed (FP32 residual arithmetic, FP64
+/* A context: the spectral-difference operators of degree p on one device
+ * (Sec. "Spectral Difference Method": N = p + 1 Chebyshev-Gauss solution
+ * points and N + 1 Legendre-Gauss flux points with both end points per
+ * direction, the Lagrange bases h_i on the former and l_i on the latter).
+ * arith: 0 = FP64 throughout; 1 = mixed (FP32 residual arithmetic, FP64
  * state, RK accumulation, metrics and diagnostics).  p in 1..6 (the FP64
- * volume kernel of p = 7 would exceed the 160 KB of LDS). */
+ * volume kernel of p = 7 would exceed the 160 KB of LDS).  Uploads the 1-D
+ * tables to the device's constant memory once per device; *out is owned by
+ * the caller and released with sdm_destroy.  SDM_EUNSUPPORTED for p outside
+ * 1..6, SDM_EINVAL for a bad arith or device. */
 sdm_status sdm_create(int device, int p, int arith, sdm_ctx** out);
 sdm_status sdm_destroy(sdm_ctx* ctx);
 
-/* Borrowed DEVICE arrays of one mesh (layouts above); they must outlive
- * every call that uses them. */
+/* Borrowed DEVICE arrays of one mesh (layouts above; Sec. "Meshing": the
+ * cubed-sphere shell of hexahedra, and Sec. "Spectral Difference Method":
+ * the Jacobian |J| and metric terms of the element map, with which the
+ * equations are solved in the transformed form of Eq. "G.E. comp"); they
+ * must outlive every call that uses them.  sdm_mesh_bind copies the
+ * neighbour table to the host once to check every code decodes into range
+ * (SDM_EINVAL otherwise) and stores the pointers. */
 typedef struct {
   int64_t n_elem;
   int64_t n_bfaces;
@@ -171,8 +181,11 @@ typedef struct {
   const void* import_v;   /* device [n_bfaces][7][N^2] or NULL (needed with import faces) */
 } sdm_params;
 
-/* Bytes of scratch (face traces, partial residual) one call needs; the
- * caller allocates it (device, 256-byte aligned) and passes it as `ws`. */
+/* Bytes of scratch (face traces of Q and of the viscous normal flux, the
+ * data the common solution and common viscous flux of Sec. "Spectral
+ * Difference Method" exchange between face neighbours, and the partial
+ * residual) one call needs; the caller allocates it (device, 256-byte
+ * aligned) and passes it as `ws`. */
 sdm_status sdm_workspace_size(const sdm_ctx* ctx, size_t* bytes);
 
 /* Device addresses, inside workspace `ws`, of the face traces a partition
@@ -185,12 +198,22 @@ sdm_status sdm_workspace_size(const sdm_ctx* ctx, size_t* bytes);
  * Residual arithmetic type.  Views only: nothing is copied. */
 sdm_status sdm_workspace_traces(const sdm_ctx* ctx, void* ws, void** q_traces, void** v_traces);
 
-/* R = dQ/dt at the solution points (device Q, R, layout [E][9][N3]). */
+/* R = dQ/dt at the solution points (device Q, R, layout [E][9][N3]): the
+ * spectral-difference residual of Sec. "Spectral Difference Method" (the
+ * procedure paragraph: Q and its gradient reconstructed at the flux points,
+ * common solution and common fluxes on the element faces, the flux
+ * divergence at the solution points) for the equations of Sec. "MHD
+ * Governing Equations" in the transformed form of Eq. "G.E. comp", i.e.
+ * R = -(div of the flux)/|J| + M with the sources of Eq. "M"; the boundary
+ * treatment of Sec. "Problem Formulation and Boundary Conditions".  `ws` is
+ * the caller's workspace of sdm_workspace_size bytes. */
 sdm_status sdm_residual(sdm_ctx* ctx, const sdm_params* prm, const double* Q, double* R,
                         void* ws, void* stream);
 
-/* One explicit Runge-Kutta stage in Shu-Osher form, fused into the last
- * pass of the residual:
+/* One explicit Runge-Kutta stage in Shu-Osher form (Sec. "Spectral
+ * Difference Method": the time integrator is a strong-stability-preserving
+ * Runge-Kutta scheme, whose stages are convex combinations of forward-Euler
+ * steps), fused into the last pass of the residual:
  *   regs[out] = sum_k alpha[k] regs[in[k]] + beta dt R(regs[cur])
  * regs: n_regs device state buffers ([E][9][N3] FP64); out may equal cur or
  * an input (each element reads before it writes).  The SSPRK(5,3) step of
@@ -210,6 +233,28 @@ typedef struct {
 sdm_status sdm_rk_stage(sdm_ctx* ctx, const sdm_params* prm, double* const* regs, int n_regs,
                         const sdm_stage* stage, double dt, void* ws, void* stream);
 
+/* The SSPRK(5,3) scheme of Sec. "Spectral Difference Method" (five stages,
+ * third order, optimal SSP coefficient 2.6506) as five sdm_stage records on
+ * four registers: u0 in regs[0] (A), u1 in B, u2 in C, u3 and u4 in D, the
+ * step's result back in A.  The Shu-Osher form of stages 4 and 5 also takes
+ * the residuals of u0 and u1; they are folded into the weights of u0, u1,
+ * u2 by L(u0) = (u1 - u0)/(beta10 dt), L(u1) = (u2 - u1)/(beta21 dt), which
+ * holds because stages 1 and 2 are single forward-Euler steps, so every
+ * stage takes one residual.  out[5] (host) receives the records (stage 1
+ * has traces_valid = 0, the others 1: each takes the previous one's
+ * output); c[5] (host, may be NULL) the time of each stage's input state in
+ * units of dt (0, beta10, ...), for callers whose boundary data depend on
+ * time.  No GPU needed. */
+sdm_status sdm_ssprk53_stages(sdm_stage* out, double* c);
+
+/* One SSPRK(5,3) step of the state in regs[0]: the five stages of
+ * sdm_ssprk53_stages in order on regs[0..3] (device, [E][9][N3] FP64 each;
+ * regs[1..3] are overwritten).  traces_valid != 0 declares that `ws` holds
+ * the face traces of regs[0] (left there by the previous step); afterwards
+ * it does.  Same errors as sdm_rk_stage. */
+sdm_status sdm_ssprk53_step(sdm_ctx* ctx, const sdm_params* prm, double* const* regs, double dt,
+                            int traces_valid, void* ws, void* stream);
+
 /* The two halves of sdm_rk_stage, for a mesh split over several GPUs: the
  * volume half (face traces of regs[cur] unless traces_valid, then every
  * element's residual except the neighbour half of the viscous flux; it
@@ -228,42 +273,13 @@ sdm_status sdm_rk_stage_volume(sdm_ctx* ctx, const sdm_params* prm, double* cons
 sdm_status sdm_rk_stage_finish(sdm_ctx* ctx, const sdm_params* prm, double* const* regs, int n_regs,
                                const sdm_stage* stage, double dt, void* ws, void* stream);
 
-/* Overlapped stage schedule.  A stage is two grid-wide passes: the volume
- * pass of an element reads its face neighbours' traces of Q, and the finish
- * pass reads their viscous face fluxes from the volume pass (Sec. "Spectral
- * Difference Method": the common solution and the common viscous flux both
- * couple face neighbours).  The volume pass is bound by arithmetic and
- * latency, the finish pass by HBM bandwidth, so sdm_rk_stage may run them
- * side by side on element chunks: chunk k's finish pass starts, on a second
- * stream of the context, once the volume passes of every chunk holding a
- * neighbour of chunk k are done.  Each element's arithmetic is unchanged, so
- * the results are bitwise those of the plain schedule.
- *
- * sdm_element_chunks (HOST, no GPU): chunks of a mesh whose neighbour table
- * nbr (host [n_elem][6], the layout above) is given.  Breadth-first levels
- * over interior faces, seeded by the elements with a face in boundary group
- * 0 (the inner wall of a shell: the levels are its radial layers) and, for a
- * piece of the mesh without such a face, by its lowest element.  order
- * (host int32 [n_elem]) receives the elements level by level, ascending
- * within a level; chunk k is order[chunk_lo[k] .. chunk_lo[k + 1]) (host
- * int64 [n_elem + 1] room), whole levels of at least min_chunk elements (a
- * short last chunk joins the one before); chunk_dep[k] (host int32 [n_elem]
- * room) is the last chunk holding a face neighbour of an element of chunk
- * k (>= k); *n_chunks their number.  SDM_EINVAL for bad sizes or codes.
- *
- * sdm_set_overlap: min_chunk > 0 enables the schedule for the context's
- * bound mesh with those chunks (2 or more; fewer leave it off), 0 disables
- * it; *n_chunks (may be NULL) receives the number of chunks in use (0 =
- * off).  Binding another mesh disables it.  sdm_rk_stage only: the split
- * halves, sdm_residual, the diagnostics and batches run as before. */
-sdm_status sdm_element_chunks(int64_t n_elem, const int32_t* nbr, int64_t min_chunk, int32_t* order,
-                              int64_t* chunk_lo, int32_t* chunk_dep, int32_t* n_chunks);
-sdm_status sdm_set_overlap(sdm_ctx* ctx, int64_t min_chunk, int32_t* n_chunks);
-
 /* Diagnostics of state Q into DEVICE out[16] (FP64): volume, mass, total
  * energy, volume-averaged KE = (1/V) int rho|u|^2/2, E_B = (1/V) int
- * |B|^2/2 (Sec. "Results"), max|div B|, L2 norm of div B, max|psi|, NaN/Inf
- * flag (1.0 if any), zeros after.  Deterministic (fixed reduction order). */
+ * |B|^2/2 (Sec. "Results"), max|div B|, L2 norm of div B (div B from the
+ * gradient of Sec. "Spectral Difference Method", the quantity the GLM
+ * cleaning of Sec. "MHD Governing Equations" drives to zero), max|psi|,
+ * NaN/Inf flag (1.0 if any), zeros after.  Quadrature: the weights of the
+ * solution points times |J|.  Deterministic (fixed reduction order). */
 sdm_status sdm_diagnostics(sdm_ctx* ctx, const sdm_params* prm, const double* Q, double* out,
                            void* ws, void* stream);
 
@@ -352,9 +368,10 @@ sdm_status sdm_batch_workspace_size(int n_items, size_t* bytes);
 
 /* Serving: advance n_items independent runs by one fused RK stage each in
  * shared launches (trace pass for items without valid traces, one volume
- * pass, one finish pass), each a grid-stride loop over the concatenated
- * elements of all runs with at most max_blocks workgroups (0: one per
- * element).  Every run gets exactly the arithmetic of sdm_rk_stage on its
+ * pass, one finish pass) over the concatenated elements of all runs, one
+ * workgroup per element; a pass with more than max_blocks elements (0: no
+ * limit) is issued as consecutive launches of at most max_blocks
+ * workgroups.  Every run gets exactly the arithmetic of sdm_rk_stage on its
  * own (results are bitwise identical alone and in a batch).  All items must
  * share p, arithmetic and device.  The descriptor table is staged through
  * library-owned pinned host memory and copied into batch_ws on `stream`. */

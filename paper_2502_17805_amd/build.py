@@ -33,7 +33,23 @@ def build(verbose=True, defines=(), out=None) -> str:
     tmp = lib + ".tmp"
     _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, kern_o, host_o, "-lgomp"])
     os.replace(tmp, lib)
+    if out is None:
+        build_c_driver(lib)
     return lib
+
+
+def build_c_driver(lib=LIB) -> str:
+    """The plain C caller of the ABI that the GPU tests run
+    (tests/c/abi_step.c): HIP runtime API only, linked against the library."""
+    root = os.path.dirname(HERE)
+    src = os.path.join(root, "tests", "c", "abi_step.c")
+    exe = os.path.join(root, "tests", "c", "abi_step")
+    if not os.path.exists(src):
+        return ""
+    _run(["gcc", "-std=c99", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", src, "-o", exe,
+          f"-L{os.path.dirname(lib)}", "-lsdmhd", "-L/opt/rocm/lib", "-lamdhip64",
+          "-Wl,-rpath,$ORIGIN/../../paper_2502_17805_amd", "-Wl,-rpath,/opt/rocm/lib"])
+    return exe
 
 
 if __name__ == "__main__":

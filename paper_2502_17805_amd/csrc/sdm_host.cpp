@@ -9,7 +9,9 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <initializer_list>
 #include <unordered_map>
+#include <utility>
 #include <vector>
 
 #ifdef _OPENMP
@@ -514,83 +516,80 @@ void sph_bins(int64_t E, int N, const double* x_sp, double rb, double rt, int n_
   for (int64_t g = 0; g < n; ++g) order[next[bin[g]]++] = (int32_t)g;
 }
 
+
+// ---------------------------------------------------------------------------
+// SSPRK(5,3) (Sec. "Spectral Difference Method": the time integrator is the
+// five-stage, third-order strong-stability-preserving Runge-Kutta scheme)
+// ---------------------------------------------------------------------------
+// Shu-Osher coefficients u(i) = sum_k a_ik u(k) + dt b_ik L(u(k)) of the
+// optimal scheme (SSP coefficient 2.6506): the published 14-digit values,
+// with the b entries corrected by a minimal-norm Newton step (< 4e-10) so
+// that the four third-order conditions hold in double precision.
+static const double kSspA[6][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0, 0, 0, 0, 0, 0},
+    {0, 1.0, 0, 0, 0, 0},
+    {0.56656131914032997754, 0, 0.43343868085967002246, 0, 0, 0},
+    {0.09299483444412999511, 0.000020903696200000000053, 0, 0.90698426185967000489, 0, 0},
+    {0.0073613226092000003456, 0.20127980325145000684, 0.0018295538968200000286, 0,
+     0.78952932024252999279, 0}};
+static const double kSspB[6][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {0.37726891519897837344, 0, 0, 0, 0, 0},
+    {0, 0.37726891516114840825, 0, 0, 0, 0},
+    {0, 0, 0.16352294101188272956, 0, 0, 0},
+    {0.00071997350394151505236, 0, 0, 0.3421769684090429351, 0, 0},
+    {0.0027771984070493497694, 0.000015679038088402258468, 0, 0, 0.29786487003033598351, 0}};
+
+void ssprk53_stages(ShuOsherStage st[5], double c[5]) {
+  const double(*a)[6] = kSspA;
+  const double(*b)[6] = kSspB;
+  // Stages 4 and 5 also need the residuals of u0 and u1.  Stages 1 and 2
+  // have a single input of weight 1 (u1 = u0 + b10 dt L(u0), u2 = u1 +
+  // b21 dt L(u1)), so those residuals are (u1 - u0)/(b10 dt) and
+  // (u2 - u1)/(b21 dt): folding them into the weights of u0, u1, u2 leaves
+  // one residual per stage and four registers (A = u0, B = u1, C = u2,
+  // D = u3 then u4; the step's result replaces u0 in A).
+  const double r0 = b[4][0] / b[1][0], s0 = b[5][0] / b[1][0], s1 = b[5][1] / b[2][1];
+  enum { A = 0, B = 1, C = 2, D = 3 };
+  auto set = [&](ShuOsherStage& x, int cur, std::initializer_list<std::pair<int, double>> in, double beta, int out) {
+    x.cur = cur;
+    x.n_in = 0;
+    for (const auto& p : in) {
+      x.in_idx[x.n_in] = p.first;
+      x.alpha[x.n_in] = p.second;
+      ++x.n_in;
+    }
+    for (int k = x.n_in; k < 4; ++k) {
+      x.in_idx[k] = 0;
+      x.alpha[k] = 0.0;
+    }
+    x.beta = beta;
+    x.out = out;
+  };
+  set(st[0], A, {{A, a[1][0]}}, b[1][0], B);
+  set(st[1], B, {{B, a[2][1]}}, b[2][1], C);
+  set(st[2], C, {{A, a[3][0]}, {C, a[3][2]}}, b[3][2], D);
+  set(st[3], D, {{A, a[4][0] - r0}, {B, a[4][1] + r0}, {D, a[4][3]}}, b[4][3], D);
+  set(st[4], D, {{A, a[5][0] - s0}, {B, a[5][1] + s0 - s1}, {C, a[5][2] + s1}, {D, a[5][4]}}, b[5][4], A);
+  // stage times from the equivalent Butcher rows: row i of the Butcher
+  // matrix is sum_k a_ik (row k) + b_ik e_k, and c_i is its sum
+  double Bt[6][5] = {{0}};
+  for (int i = 1; i < 6; ++i)
+    for (int k = 0; k < i; ++k) {
+      for (int j = 0; j < 5; ++j) Bt[i][j] += a[i][k] * Bt[k][j];
+      Bt[i][k] += b[i][k];
+    }
+  for (int i = 0; i < 5; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < 5; ++j) s += Bt[i][j];
+    c[i] = s;
+  }
+}
+
 }  // namespace sdm
 
 namespace sdm {
-
-int element_chunks(int64_t E, const int32_t* nbr, int64_t min_chunk, int32_t* order, std::vector<int64_t>& lo,
-                   std::vector<int32_t>& dep) {
-  if (E < 1 || min_chunk < 1) return 1;
-  // breadth-first levels over interior faces
-  std::vector<int32_t> level((size_t)E, -1);
-  std::vector<int64_t> queue;
-  queue.reserve((size_t)E);
-  for (int64_t e = 0; e < E; ++e)
-    for (int f = 0; f < 6; ++f) {
-      const int32_t c = nbr[e * 6 + f];
-      if (c < 0 && ((-(int64_t)c - 1) & 3) == 0 && level[e] < 0) {
-        level[e] = 0;
-        queue.push_back(e);
-      }
-    }
-  size_t head = 0;
-  int64_t next_seed = 0;
-  int32_t top = queue.empty() ? -1 : 0;  // highest level assigned so far
-  for (;;) {
-    while (head < queue.size()) {
-      const int64_t e = queue[head++];
-      for (int f = 0; f < 6; ++f) {
-        const int32_t c = nbr[e * 6 + f];
-        if (c < 0) continue;
-        const int64_t en = c >> 6;
-        if (level[en] < 0) {
-          level[en] = level[e] + 1;
-          top = std::max(top, level[en]);
-          queue.push_back(en);
-        }
-      }
-    }
-    // a piece not reached from the seeds starts at the next free level
-    while (next_seed < E && level[next_seed] >= 0) ++next_seed;
-    if (next_seed == E) break;
-    level[next_seed] = ++top;
-    queue.push_back(next_seed);
-  }
-  // order: level by level, ascending element index within a level
-  int32_t n_lev = 0;
-  for (int64_t e = 0; e < E; ++e) n_lev = std::max(n_lev, level[e] + 1);
-  std::vector<int64_t> cnt((size_t)n_lev + 1, 0);
-  for (int64_t e = 0; e < E; ++e) ++cnt[level[e] + 1];
-  for (int32_t l = 0; l < n_lev; ++l) cnt[l + 1] += cnt[l];
-  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
-  for (int64_t e = 0; e < E; ++e) order[pos[level[e]]++] = (int32_t)e;
-  // chunks of whole levels, each at least min_chunk elements (a short last
-  // chunk joins the one before it)
-  lo.assign(1, 0);
-  for (int32_t l = 0; l < n_lev; ++l)
-    if (cnt[l + 1] - lo.back() >= min_chunk) lo.push_back(cnt[l + 1]);
-  if (lo.back() != E) {
-    if (lo.size() > 1) lo.back() = E;
-    else lo.push_back(E);
-  }
-  const int K = (int)lo.size() - 1;
-  std::vector<int32_t> chunk_of((size_t)E);
-  for (int k = 0; k < K; ++k)
-    for (int64_t i = lo[k]; i < lo[k + 1]; ++i) chunk_of[order[i]] = k;
-  dep.assign((size_t)K, 0);
-  for (int k = 0; k < K; ++k) {
-    int32_t m = k;
-    for (int64_t i = lo[k]; i < lo[k + 1]; ++i) {
-      const int64_t e = order[i];
-      for (int f = 0; f < 6; ++f) {
-        const int32_t c = nbr[e * 6 + f];
-        if (c >= 0) m = std::max(m, chunk_of[c >> 6]);
-      }
-    }
-    dep[k] = m;
-  }
-  return 0;
-}
 
 }  // namespace sdm
 

@@ -33,16 +33,20 @@ int box_build(int nx, int ny, int nz, double Lx, double Ly, double Lz, int perio
 void sph_bins(int64_t E, int N, const double* x_sp, double rb, double rt, int n_r, int n_th, int32_t* order,
               int64_t* offsets);
 
-// Element chunks for the overlapped stage schedule: breadth-first levels over
-// interior faces, seeded by the elements with a face in boundary group 0 (the
-// inner wall of a shell, whose levels are then its radial layers) and, for
-// pieces without such a face, by their lowest element.  order[E] lists the
-// elements level by level (ascending within a level); chunk k covers
-// order[lo[k] .. lo[k + 1]), whole levels of at least min_chunk elements (a
-// short last chunk joins the previous one); dep[k] >= k is the last chunk
-// holding a face neighbour of an element of chunk k.  Nonzero on bad sizes.
-int element_chunks(int64_t E, const int32_t* nbr, int64_t min_chunk, int32_t* order, std::vector<int64_t>& lo,
-                   std::vector<int32_t>& dep);
+// One explicit Runge-Kutta stage in Shu-Osher form on numbered state
+// registers: regs[out] = sum_k alpha[k] regs[in_idx[k]] + beta dt R(regs[cur]).
+struct ShuOsherStage {
+  int cur, n_in, in_idx[4];
+  double alpha[4];
+  int out;
+  double beta;
+};
+
+// The SSPRK(5,3) scheme named in Sec. "Spectral Difference Method" as five
+// such stages on four registers (u0 in register 0, the step's result back in
+// register 0), and c[5]: the time, in units of dt, of the state each stage
+// takes the residual of.
+void ssprk53_stages(ShuOsherStage st[5], double c[5]);
 
 // Initial background of Sec. "Initial Conditions": the polytrope, or the
 // almost flux-balanced profile (entropy gradient from the outward heat flux

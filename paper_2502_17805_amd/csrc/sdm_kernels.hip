@@ -101,7 +101,6 @@ struct Launch {
   int32_t n_run;
   int64_t n_work;               // work items end here (one element each)
   int64_t w0;                   // first work item of this launch (one per workgroup)
-  const int32_t* order;         // single run: element of work item w (NULL: w itself)
 };
 
 // Device-side view of one run's descriptor with every array pointer in the
@@ -189,7 +188,7 @@ __device__ __forceinline__ Run<T> view(const Launch& L, int64_t w) {
   Run<T> r;
   if (L.many == nullptr) {
     fill_run(r, L.one);
-    r.e = L.order ? (int64_t)((const GBL int32_t*)L.order)[w] : w;
+    r.e = w;
     return r;
   }
   const GBL int64_t* pre = (const GBL int64_t*)L.prefix;
@@ -1368,25 +1367,7 @@ struct sdm_ctx {
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> marks;  // (kernel id, start event index)
-  // overlapped stage schedule (sdm_set_overlap): element chunks of whole
-  // breadth-first levels; chunk k's finish pass runs on `aux` once the volume
-  // passes of chunks 0..dep[k] are done, beside the later volume passes
-  int32_t* order = nullptr;        // device [E]: elements chunk by chunk
-  std::vector<int64_t> chunk_lo;   // [K + 1] ranges in `order`
-  std::vector<int32_t> chunk_dep;  // [K]
-  hipStream_t aux = nullptr;
-  std::vector<hipEvent_t> ev_vol;  // [K] volume pass of chunk k done
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
-
-namespace {
-void overlap_release(sdm_ctx* c) {
-  if (c->order) (void)hipFree(c->order);
-  c->order = nullptr;
-  c->chunk_lo.clear();
-  c->chunk_dep.clear();
-}
-}  // namespace
 
 namespace {
 
@@ -1659,11 +1640,6 @@ sdm_status sdm_destroy(sdm_ctx* c) {
   if (c) {
     (void)hipSetDevice(c->device);
     for (hipEvent_t h : c->ev) (void)hipEventDestroy(h);
-    overlap_release(c);
-    for (hipEvent_t h : c->ev_vol) (void)hipEventDestroy(h);
-    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
-    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
-    if (c->aux) (void)hipStreamDestroy(c->aux);
   }
   delete c;
   return SDM_OK;
@@ -1718,7 +1694,6 @@ sdm_status sdm_mesh_bind(sdm_ctx* c, const sdm_mesh* m) {
       ++ng[g];
     }
   }
-  overlap_release(c);  // chunks belong to the previous mesh
   c->mesh = *m;
   for (int g = 0; g < 4; ++g) c->n_group[g] = ng[g];
   c->bound = true;
@@ -1740,56 +1715,6 @@ sdm_status sdm_background_profile(const sdm_background* bg, int64_t n, const dou
     default: return fail(SDM_EINVAL, "background_profile: need gamma > 1, Rgas, GM, rho_b, N_rho > 0, 0 < rb < rt "
                                      "and kappa > 0 for the flux-balanced profile");
   }
-}
-
-sdm_status sdm_element_chunks(int64_t n_elem, const int32_t* nbr, int64_t min_chunk, int32_t* order,
-                              int64_t* chunk_lo, int32_t* chunk_dep, int32_t* n_chunks) {
-  if (n_elem < 1 || n_elem >= ((int64_t)1 << 25) || min_chunk < 1)
-    return fail(SDM_EINVAL, "element_chunks: 1 <= n_elem < 2^25 and min_chunk >= 1 required");
-  if (!nbr || !order || !chunk_lo || !chunk_dep || !n_chunks) return fail(SDM_EINVAL, "element_chunks: NULL argument");
-  for (int64_t i = 0; i < n_elem * 6; ++i)
-    if (nbr[i] >= 0 && ((nbr[i] >> 6) >= n_elem || ((nbr[i] >> 3) & 7) > 5))
-      return fail(SDM_EINVAL, "element_chunks: neighbour code out of range");
-  std::vector<int64_t> lo;
-  std::vector<int32_t> dep;
-  if (element_chunks(n_elem, nbr, min_chunk, order, lo, dep)) return fail(SDM_EINVAL, "element_chunks failed");
-  std::copy(lo.begin(), lo.end(), chunk_lo);
-  std::copy(dep.begin(), dep.end(), chunk_dep);
-  *n_chunks = (int32_t)dep.size();
-  return SDM_OK;
-}
-
-sdm_status sdm_set_overlap(sdm_ctx* c, int64_t min_chunk, int32_t* n_chunks) {
-  if (!c) return fail(SDM_EINVAL, "set_overlap: NULL context");
-  if (min_chunk < 0) return fail(SDM_EINVAL, "set_overlap: min_chunk >= 0 required");
-  HIP_TRY(hipSetDevice(c->device));
-  overlap_release(c);
-  if (n_chunks) *n_chunks = 0;
-  if (min_chunk == 0) return SDM_OK;
-  if (!c->bound) return fail(SDM_ESTATE, "set_overlap: no mesh bound");
-  const int64_t E = c->mesh.n_elem;
-  std::vector<int32_t> nb((size_t)E * 6), order((size_t)E);
-  HIP_TRY(hipMemcpy(nb.data(), c->mesh.nbr, sizeof(int32_t) * nb.size(), hipMemcpyDeviceToHost));
-  std::vector<int64_t> lo;
-  std::vector<int32_t> dep;
-  if (element_chunks(E, nb.data(), min_chunk, order.data(), lo, dep)) return fail(SDM_EINVAL, "set_overlap: chunking failed");
-  const int K = (int)dep.size();
-  if (K >= 2) {
-    HIP_TRY(hipMalloc(&c->order, sizeof(int32_t) * (size_t)E));
-    HIP_TRY(hipMemcpy(c->order, order.data(), sizeof(int32_t) * (size_t)E, hipMemcpyHostToDevice));
-    c->chunk_lo = lo;
-    c->chunk_dep = dep;
-    if (!c->aux) HIP_TRY(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
-    while ((int)c->ev_vol.size() < K) {
-      hipEvent_t h;
-      HIP_TRY(hipEventCreateWithFlags(&h, hipEventDisableTiming));
-      c->ev_vol.push_back(h);
-    }
-    if (!c->ev_in) HIP_TRY(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
-    if (!c->ev_out) HIP_TRY(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
-  }
-  if (n_chunks) *n_chunks = K >= 2 ? K : 0;
-  return SDM_OK;
 }
 
 sdm_status sdm_workspace_size(const sdm_ctx* c, size_t* bytes) {
@@ -1855,37 +1780,6 @@ sdm_status stage_parts(sdm_ctx* c, const sdm_params* p, double* const* regs, int
   r.write_traces = 1;
   r.fuse = 1;  // k_volume forms the stage output
   Launch L = single(r);
-  if (parts == 3 && c->order) {
-    // overlapped schedule: volume passes chunk by chunk on the caller's
-    // stream; chunk k's finish pass on `aux` after the volume pass of chunk
-    // dep[k] (which completes every neighbour's viscous face flux and every
-    // read of chunk k's old face traces); the caller's stream then waits for
-    // the last finish pass
-    if (!stg->traces_valid && (st = run(c, 0, L, s)) != SDM_OK) return st;
-    const int K = (int)c->chunk_dep.size();
-    HIP_TRY(hipEventRecord(c->ev_in, s));
-    HIP_TRY(hipStreamWaitEvent(c->aux, c->ev_in, 0));
-    Launch Lc = L;
-    Lc.order = c->order;
-    int kf = 0;
-    for (int k = 0; k < K; ++k) {
-      Lc.w0 = c->chunk_lo[k];
-      Lc.n_work = c->chunk_lo[k + 1];
-      if ((st = run(c, 1, Lc, s)) != SDM_OK) return st;
-      if (kf < K && c->chunk_dep[kf] <= k) {
-        HIP_TRY(hipEventRecord(c->ev_vol[k], s));
-        HIP_TRY(hipStreamWaitEvent(c->aux, c->ev_vol[k], 0));
-      }
-      for (; kf < K && c->chunk_dep[kf] <= k; ++kf) {
-        Lc.w0 = c->chunk_lo[kf];
-        Lc.n_work = c->chunk_lo[kf + 1];
-        if ((st = run(c, 4, Lc, c->aux)) != SDM_OK) return st;
-      }
-    }
-    HIP_TRY(hipEventRecord(c->ev_out, c->aux));
-    HIP_TRY(hipStreamWaitEvent(s, c->ev_out, 0));
-    return SDM_OK;
-  }
   if (parts & 1) {
     if (!stg->traces_valid && (st = run(c, 0, L, s)) != SDM_OK) return st;
     if ((st = run(c, 1, L, s)) != SDM_OK) return st;
@@ -1908,6 +1802,41 @@ sdm_status sdm_rk_stage_volume(sdm_ctx* c, const sdm_params* p, double* const* r
 sdm_status sdm_rk_stage_finish(sdm_ctx* c, const sdm_params* p, double* const* regs, int n_regs,
                                const sdm_stage* stg, double dt, void* ws, void* stream) {
   return stage_parts(c, p, regs, n_regs, stg, dt, ws, stream, 2, "rk_stage_finish");
+}
+
+sdm_status sdm_ssprk53_stages(sdm_stage* out, double* c) {
+  if (!out) return fail(SDM_EINVAL, "ssprk53_stages: out is NULL");
+  ShuOsherStage st[5];
+  double cc[5];
+  ssprk53_stages(st, cc);
+  for (int i = 0; i < 5; ++i) {
+    sdm_stage& o = out[i];
+    std::memset(&o, 0, sizeof o);
+    o.n_in = st[i].n_in;
+    for (int k = 0; k < 4; ++k) {
+      o.in_idx[k] = st[i].in_idx[k];
+      o.alpha[k] = st[i].alpha[k];
+    }
+    o.cur = st[i].cur;
+    o.out = st[i].out;
+    o.beta = st[i].beta;
+    o.traces_valid = 1;  // each stage's input is the previous stage's output
+  }
+  out[0].traces_valid = 0;
+  if (c) std::copy(cc, cc + 5, c);
+  return SDM_OK;
+}
+
+sdm_status sdm_ssprk53_step(sdm_ctx* c, const sdm_params* p, double* const* regs, double dt, int traces_valid,
+                            void* ws, void* stream) {
+  if (!regs) return fail(SDM_EINVAL, "ssprk53_step: NULL argument");
+  sdm_stage st[5];
+  sdm_status s = sdm_ssprk53_stages(st, nullptr);
+  if (s != SDM_OK) return s;
+  st[0].traces_valid = traces_valid ? 1 : 0;
+  for (int i = 0; i < 5; ++i)
+    if ((s = stage_parts(c, p, regs, 4, &st[i], dt, ws, stream, 3, "ssprk53_step")) != SDM_OK) return s;
+  return SDM_OK;
 }
 
 sdm_status sdm_diagnostics(sdm_ctx* c, const sdm_params* p, const double* Q, double* out, void* ws,

@@ -10,11 +10,11 @@ Entry points mirror include/sdmhd.h:
   Solver(mesh, arith)              context + device copies of the mesh
   Solver.residual(prm, Q)          R = dQ/dt                 (sdm_residual)
   Solver.stage(prm, regs, st, dt)  one fused Shu-Osher stage (sdm_rk_stage)
-  Solver.step(prm, dt)             one SSPRK(5,3) step = five stages
+  Solver.step(prm, dt)             one SSPRK(5,3) step     (sdm_ssprk53_step)
   Solver.diagnostics(prm, Q)       volume, mass, energy, KE, E_B, div B, ...
   sph_bins / Solver.sph_profiles   spherical-component sums per (r, theta) bin
   background_profile(r, ...)       polytrope / flux-balanced initial background
-  Solver.set_overlap(min_chunk)    opt-in overlapped stage schedule
+  ssp53_stages()                   the SSPRK(5,3) stages (sdm_ssprk53_stages)
 """
 from __future__ import annotations
 
@@ -101,8 +101,8 @@ _lib.sdm_diagnostics.argtypes = [_vp, C.POINTER(Params), _vp, _vp, _vp, _vp]
 _lib.sdm_sph_bins.argtypes = [C.c_int64, C.c_int, _vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp, _vp]
 _lib.sdm_sph_profiles.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp, _vp]
 _lib.sdm_background_profile.argtypes = [C.POINTER(BackgroundDesc), C.c_int64, _vp, _vp, _vp, _vp]
-_lib.sdm_element_chunks.argtypes = [C.c_int64, _vp, C.c_int64, _vp, _vp, _vp, C.POINTER(C.c_int32)]
-_lib.sdm_set_overlap.argtypes = [_vp, C.c_int64, C.POINTER(C.c_int32)]
+_lib.sdm_ssprk53_stages.argtypes = [C.POINTER(Stage), C.POINTER(C.c_double)]
+_lib.sdm_ssprk53_step.argtypes = [_vp, C.POINTER(Params), C.POINTER(C.c_void_p), C.c_double, C.c_int, _vp, _vp]
 _lib.sdm_batch_workspace_size.argtypes = [C.c_int, C.POINTER(C.c_size_t)]
 _lib.sdm_batch_stage.argtypes = [C.POINTER(BatchItem), C.c_int, _vp, C.c_size_t, C.c_int, _vp]
 _lib.sdm_profile_enable.argtypes = [_vp, C.c_int]
@@ -111,7 +111,7 @@ for _f in ("sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes", "sdm_box_build
            "sdm_create", "sdm_destroy", "sdm_mesh_bind", "sdm_workspace_size", "sdm_residual",
            "sdm_rk_stage", "sdm_diagnostics", "sdm_profile_enable", "sdm_profile_read",
            "sdm_batch_workspace_size", "sdm_batch_stage", "sdm_workspace_traces", "sdm_rk_stage_volume",
-           "sdm_rk_stage_finish", "sdm_sph_bins", "sdm_sph_profiles", "sdm_element_chunks", "sdm_set_overlap",
+           "sdm_rk_stage_finish", "sdm_sph_bins", "sdm_sph_profiles", "sdm_ssprk53_stages", "sdm_ssprk53_step",
            "sdm_background_profile"):
     getattr(_lib, _f).restype = C.c_int
 
@@ -120,7 +120,7 @@ EXPORTED = ("sdm_last_error", "sdm_version", "sdm_shell_sizes", "sdm_shell_build
             "sdm_workspace_size", "sdm_residual", "sdm_rk_stage", "sdm_diagnostics",
             "sdm_profile_enable", "sdm_profile_read", "sdm_batch_workspace_size", "sdm_batch_stage",
             "sdm_workspace_traces", "sdm_rk_stage_volume", "sdm_rk_stage_finish", "sdm_sph_bins",
-            "sdm_sph_profiles", "sdm_element_chunks", "sdm_set_overlap", "sdm_background_profile")
+            "sdm_sph_profiles", "sdm_ssprk53_stages", "sdm_ssprk53_step", "sdm_background_profile")
 KERNELS = ("traces", "volume", "volume_diag", "finish_residual", "finish_stage")
 
 
@@ -240,19 +240,6 @@ def background_profile(r, GM=1.0, Rgas=1.0, gamma=5.0 / 3.0, rb=0.70, rt=0.98, r
     return tuple(out)
 
 
-def element_chunks(nbr: np.ndarray, min_chunk: int):
-    """Element chunks of the overlapped stage schedule (sdm_element_chunks):
-    (order int32 [E], chunk_lo int64 [K + 1], chunk_dep int32 [K])."""
-    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
-    E = nbr.shape[0]
-    order = np.zeros(E, dtype=np.int32)
-    lo = np.zeros(E + 1, dtype=np.int64)
-    dep = np.zeros(E, dtype=np.int32)
-    k = C.c_int32()
-    _check(_lib.sdm_element_chunks(E, _p(nbr), int(min_chunk), _p(order), _p(lo), _p(dep), C.byref(k)))
-    return order, lo[:k.value + 1].copy(), dep[:k.value].copy()
-
-
 def face_point_map(N: int) -> np.ndarray:
     """[8][N^2]: for orientation code o, the neighbour's face-point index
     a' + N b' of this side's face point a + N b (the map of include/sdmhd.h)."""
@@ -339,41 +326,21 @@ def tables(p: int):
     return xs, xf, I, D, W
 
 
-# Shu-Osher coefficients (alpha_ik, beta_ik) of the optimal five-stage,
-# third-order SSP Runge-Kutta scheme named by the paper (Sec. "Spectral
-# Difference Method"): published 14-digit values with the beta entries
-# corrected by a minimal-norm Newton step so that the third-order conditions
-# hold in double precision.
-SSP53_ALPHA = {(1, 0): 1.0, (2, 1): 1.0,
-               (3, 0): 0.56656131914032997754, (3, 2): 0.43343868085967002246,
-               (4, 0): 0.09299483444412999511, (4, 1): 0.000020903696200000000053,
-               (4, 3): 0.90698426185967000489,
-               (5, 0): 0.0073613226092000003456, (5, 1): 0.20127980325145000684,
-               (5, 2): 0.0018295538968200000286, (5, 4): 0.78952932024252999279}
-SSP53_BETA = {(1, 0): 0.37726891519897837344, (2, 1): 0.37726891516114840825,
-              (3, 2): 0.16352294101188272956, (4, 0): 0.00071997350394151505236,
-              (4, 3): 0.3421769684090429351, (5, 0): 0.0027771984070493497694,
-              (5, 1): 0.000015679038088402258468, (5, 4): 0.29786487003033598351}
-
-
 def ssp53_stages():
-    """The five stages on four registers A=u0, B=u1, C=u2, D=u3/u4 (out of
-    stage 5 -> A).  The stored residuals L(u0), L(u1) that stages 4 and 5
-    need are replaced by (u1 - u0)/(beta10 dt) and (u2 - u1)/(beta21 dt), so
-    each stage is one fused residual + linear combination."""
-    a, b = SSP53_ALPHA, SSP53_BETA
-    r0 = b[(4, 0)] / b[(1, 0)]
-    s0 = b[(5, 0)] / b[(1, 0)]
-    s1 = b[(5, 1)] / b[(2, 1)]
-    A, B, Cc, D = 0, 1, 2, 3
-    return [
-        (A, [(A, 1.0)], b[(1, 0)], B),
-        (B, [(B, 1.0)], b[(2, 1)], Cc),
-        (Cc, [(A, a[(3, 0)]), (Cc, a[(3, 2)])], b[(3, 2)], D),
-        (D, [(A, a[(4, 0)] - r0), (B, a[(4, 1)] + r0), (D, a[(4, 3)])], b[(4, 3)], D),
-        (D, [(A, a[(5, 0)] - s0), (B, a[(5, 1)] + s0 - s1), (Cc, a[(5, 2)] + s1), (D, a[(5, 4)])],
-         b[(5, 4)], A),
-    ]
+    """The five SSPRK(5,3) stages on four registers as the library defines
+    them (sdm_ssprk53_stages): a list of (cur, [(input register, alpha)],
+    beta, out)."""
+    st = (Stage * 5)()
+    _check(_lib.sdm_ssprk53_stages(st, None))
+    return [(x.cur, [(x.in_idx[k], x.alpha[k]) for k in range(x.n_in)], x.beta, x.out) for x in st]
+
+
+def ssp53_stage_times():
+    """Time of each stage's input state in units of dt (sdm_ssprk53_stages)."""
+    st = (Stage * 5)()
+    c = (C.c_double * 5)()
+    _check(_lib.sdm_ssprk53_stages(st, c))
+    return list(c)
 
 
 class Solver:
@@ -410,13 +377,6 @@ class Solver:
                 self._h = None
         except Exception:
             pass
-
-    def set_overlap(self, min_chunk: int) -> int:
-        """Enable (min_chunk > 0) or disable (0) the overlapped stage schedule
-        (sdm_set_overlap); returns the number of chunks in use (0 = off)."""
-        k = C.c_int32()
-        _check(_lib.sdm_set_overlap(self._h, int(min_chunk), C.byref(k)))
-        return k.value
 
     def trace_views(self):
         """(q_traces [E][6][9][N^2], v_traces [E][6][7][N^2]) as tensors viewing
@@ -474,9 +434,11 @@ class Solver:
             self._traces_of = out if regs is self.regs else None
 
     def step(self, prm: Params, dt: float):
-        """One SSPRK(5,3) step of the state in register 0."""
-        for cur, inputs, beta, out in ssp53_stages():
-            self.stage(prm, cur, inputs, beta, out, dt)
+        """One SSPRK(5,3) step of the state in register 0 (sdm_ssprk53_step)."""
+        arr = (C.c_void_p * 4)(*[r.data_ptr() for r in self.regs[:4]])
+        _check(_lib.sdm_ssprk53_step(self._h, C.byref(prm), arr, dt, 1 if self._traces_of == 0 else 0,
+                                     self.ws.data_ptr(), self._stream()))
+        self._traces_of = 0
 
     def profile(self, enable: bool):
         _check(_lib.sdm_profile_enable(self._h, 1 if enable else 0))

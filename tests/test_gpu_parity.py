@@ -125,6 +125,37 @@ def test_ssprk53_steps_c1(sd, oracle):
         assert (err <= TOL * scale).all(), (step, err / scale)
 
 
+# Bound of the FP32-mixed run against the FP64 oracle: per variable, the
+# state after each of ten C1 steps within MIXED_STEP_TOL of
+# max|u_v| + dt T_v (FP32 residual arithmetic: a relative error of about
+# 1e-6 of the term scale per residual, FP64 accumulation of the stages)
+MIXED_STEP_TOL = 1e-5
+
+
+def test_ssprk53_steps_c1_mixed(sd, oracle):
+    """The C1 run in FP32-mixed arithmetic: 10 SSPRK(5,3) steps on the
+    48-element shell, every step's state against the FP64 oracle's within
+    the stated bound (and not bitwise: the residual really is FP32)."""
+    ml, mo, bg, Q, pr = _c1(sd, oracle)
+    dt = inp.time_step(Q, mo.get("S_sp") / mo.get("detJ_sp")[:, None, None, :], pr["c_h"], 0.1)
+    s = sd.Solver(ml, arith=1)
+    pg, po, _ = _both(sd, oracle, pr)
+    s.set_state(Q)
+    qo = Q.copy()
+    worst = 0.0
+    for step in range(10):
+        _, ts = mo.residual(po, qo, with_scale=True)
+        s.step(pg, dt)
+        qo = mo.step(po, qo, dt)
+        qg = s.state.cpu().numpy()
+        rel = np.abs(qg - qo).max(axis=(0, 2)) / (np.abs(qo).max(axis=(0, 2)) + dt * ts)
+        worst = max(worst, rel.max())
+        assert np.isfinite(qg).all()
+        assert (rel <= MIXED_STEP_TOL).all(), (step, rel)
+    print(f"c1 mixed: worst relative state error over 10 steps {worst:.2e}", flush=True)
+    assert worst > 1e-13
+
+
 def test_single_stage_each_kind(sd, oracle):
     """Each of the five fused stages separately (inputs from the oracle's own
     Shu-Osher stages), so a wrong coefficient or register shows up alone."""

@@ -54,6 +54,20 @@ def test_c2_first_step(sd, oracle, N_rho, seed):
     assert (err <= TOL * scale).all(), err / scale
 
 
+@pytest.mark.parametrize("N_rho,seed", [(3.0, 1), (5.0, 2)])
+def test_c2_step1_residual(sd, oracle, N_rho, seed):
+    """6,912-element shell, p = 5: the step-1 residual itself, point by point
+    against the oracle's, within 1e-12 of the term scale per variable."""
+    import torch
+    ml, mo, Q, pr, dt = _setup(sd, oracle, 12, 8, 5, N_rho, seed)
+    print(f"c2 residual N_rho={N_rho} seed={seed} E={ml.E}", flush=True)
+    s = sd.Solver(ml)
+    Rg = s.residual(sd.make_params(**pr), torch.from_numpy(Q).cuda()).cpu().numpy()
+    Ro, ts = mo.residual(oracle.make_params(**pr), Q, with_scale=True)
+    err = np.abs(Rg - Ro).max(axis=(0, 2))
+    assert (err <= TOL * ts).all(), err / ts
+
+
 def test_c2_ten_steps(sd, oracle):
     """6,912-element shell, N_rho = 5: every one of ten steps."""
     ml, mo, Q, pr, dt = _setup(sd, oracle, 12, 8, 5, 5.0, 2)
@@ -73,14 +87,20 @@ def test_c2_ten_steps(sd, oracle):
 
 
 def test_c4_full_size_stage(sd, oracle):
-    """55,296-element shell, p = 5 (the benchmark workload): the first fused
-    stage u1 = u0 + b10 dt L(u0) in FP64 over every element, and the
-    FP32-mixed residual arithmetic within 1e-5 of the same scale."""
+    """55,296-element shell, p = 5 (the benchmark workload): the residual and
+    the first fused stage u1 = u0 + b10 dt L(u0) in FP64 over every element,
+    and the FP32-mixed residual arithmetic within 1e-5 of the same scale."""
     import torch
     ml, mo, Q, pr, dt = _setup(sd, oracle, 24, 16, 5, 5.0, 2)
     print(f"c4 full size E={ml.E}", flush=True)
     po = oracle.make_params(**pr)
     Ro, ts = mo.residual(po, Q, with_scale=True)
+    # the residual itself, every element
+    s = sd.Solver(ml)
+    Rg = s.residual(sd.make_params(**pr), torch.from_numpy(Q).cuda()).cpu().numpy()
+    err = np.abs(Rg - Ro).max(axis=(0, 2))
+    assert (err <= TOL * ts).all(), err / ts
+    del s, Rg
     _, b, _ = oracle.ssprk53_table()
     cur, inputs, beta, out = sd.ssp53_stages()[0]
     want = Q + dt * b[1, 0] * Ro

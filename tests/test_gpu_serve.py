@@ -138,3 +138,43 @@ def test_batch_rejects_mixed_degrees(srv):
     rc = sd._lib.sdm_batch_stage(items, 2, bws.data_ptr(), nb.value, 0,
                                  C.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert rc != sd.SDM_OK and b"share p" in sd._lib.sdm_last_error()
+
+
+def test_batched_stages_match_oracle(srv, oracle):
+    """Two runs of different shell sizes and backgrounds advanced together
+    by sdm_batch_stage (one launch sequence per stage over both runs'
+    elements): each run's state after two SSPRK(5,3) steps against the FP64
+    oracle's, within 1e-12 of max|u_v| + dt T_v."""
+    import torch
+
+    from paper_2502_17805_amd import sdmhd as sd
+    runs = []
+    for (Nz, Nr, N_rho, seed) in ((2, 1, 3.0, 1000), (2, 2, 5.0, 1001)):
+        m = sd.shell(Nz, Nr, 5)
+        mo = oracle.Mesh.shell(6, Nz, Nr)
+        bg = inp.Background(N_rho)
+        Q = inp.shell_state(m.x_sp, bg, seed)
+        pr = inp.run_params(seed, bg)
+        ch = inp.glm_speed(Q)
+        pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
+        s = sd.Solver(m)
+        s.set_state(torch.from_numpy(Q))
+        runs.append((s, sd.make_params(**pr), oracle.make_params(**pr), mo, Q))
+    dt = 2e-3
+    import ctypes as C
+    nb = C.c_size_t()
+    sd._check(sd._lib.sdm_batch_workspace_size(len(runs), C.byref(nb)))
+    bws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for _ in range(2):
+        _batch_step(sd, [r[0] for r in runs], [r[1] for r in runs], dt, bws, int(nb.value), stream)
+    torch.cuda.synchronize()
+    for s, _, po, mo, Q in runs:
+        qo, scale = Q, None
+        for _ in range(2):
+            _, ts = mo.residual(po, qo, with_scale=True)
+            scale = ts if scale is None else np.maximum(scale, ts)
+            qo = mo.step(po, qo, dt)
+        got = s.state.cpu().numpy()
+        err = np.abs(got - qo).max(axis=(0, 2)) / (np.abs(qo).max(axis=(0, 2)) + dt * scale)
+        assert (err <= 1e-12).all(), err

@@ -163,81 +163,28 @@ def test_sph_bins_host(sd, oracle):
         sd.sph_bins(m, 0, 4)
 
 
-def _check_chunks(nbr, order, lo, dep, min_chunk):
-    E = nbr.shape[0]
-    assert np.array_equal(np.sort(order), np.arange(E))
-    K = len(dep)
-    assert lo[0] == 0 and lo[-1] == E and (np.diff(lo) > 0).all()
-    if K > 1:
-        assert (np.diff(lo) >= min_chunk).all()
-    chunk = np.zeros(E, dtype=np.int64)
-    for k in range(K):
-        chunk[order[lo[k]:lo[k + 1]]] = k
-    # dep[k] = the last chunk holding a face neighbour of chunk k (or k)
-    want = np.arange(K)
-    for e in range(E):
-        for c in nbr[e]:
-            if c >= 0:
-                want[chunk[e]] = max(want[chunk[e]], chunk[c >> 6])
-    assert np.array_equal(dep, want)
-    return chunk
-
-
-@pytest.mark.parametrize("Nz,Nr", [(2, 2), (4, 3), (3, 5)])
-def test_element_chunks_shell_layers(sd, Nz, Nr):
-    """On a shell the breadth-first levels from the inner wall are the radial
-    layers: with min_chunk = 1 each chunk is one layer (ascending element
-    index within it) and depends on the next layer only."""
-    m = sd.shell(Nz, Nr, 3)
-    order, lo, dep = sd.element_chunks(m.nbr, 1)
-    chunk = _check_chunks(m.nbr, order, lo, dep, 1)
-    e = np.arange(m.E)
-    layer = (e // (Nz * Nz)) % Nr
-    assert np.array_equal(chunk, layer)
-    for k in range(len(dep)):
-        assert (np.diff(order[lo[k]:lo[k + 1]]) > 0).all()
-    assert np.array_equal(dep, np.minimum(np.arange(Nr) + 1, Nr - 1))
-    # larger chunks hold whole layers
-    order2, lo2, dep2 = sd.element_chunks(m.nbr, 2 * 6 * Nz * Nz)
-    _check_chunks(m.nbr, order2, lo2, dep2, 2 * 6 * Nz * Nz)
-    assert all(x % (6 * Nz * Nz) == 0 for x in lo2)
-
-
-@pytest.mark.parametrize("periodic", [0, 7])
-def test_element_chunks_box(sd, periodic):
-    """A box (no inner-wall faces, possibly periodic): levels from element
-    0; every chunk still knows its last neighbouring chunk."""
-    m = sd.box(4, 3, 5, 2, periodic=periodic)
-    for mc in (1, 7, 25, 1000):
-        order, lo, dep = sd.element_chunks(m.nbr, mc)
-        _check_chunks(m.nbr, order, lo, dep, mc)
-    with pytest.raises(sd.SdmError):
-        sd.element_chunks(m.nbr, 0)
-    bad = m.nbr.copy()
-    bad[0, 0] = (10 ** 6) << 6
-    with pytest.raises(sd.SdmError):
-        sd.element_chunks(bad, 4)
-
-
-def test_element_chunks_disconnected(sd):
-    """Pieces of a mesh not reached from the inner wall (a shard's elements
-    joined only through import faces) start their own levels."""
-    m = sd.shell(2, 3, 3)
-    nbr = m.nbr.copy()
-    # cut every face between layer 0 and layer 1 (turn them into group-3 faces)
-    Nz = 2
-    layer = (np.arange(m.E) // (Nz * Nz)) % 3
-    bf = 0
-    for e in range(m.E):
-        for f in range(6):
-            c = nbr[e, f]
-            if c >= 0 and {layer[e], layer[c >> 6]} == {0, 1}:
-                nbr[e, f] = -(1 + 3 + 4 * bf)
-                bf += 1
-    order, lo, dep = sd.element_chunks(nbr, 1)
-    chunk = _check_chunks(nbr, order, lo, dep, 1)
-    assert set(chunk[layer == 0]) == {0}
-    assert (chunk[layer > 0] > 0).all()
+def test_ssprk53_stages_reproduce_the_scheme(sd, oracle):
+    """The five register stages the library defines (sdm_ssprk53_stages, no
+    GPU) advance a linear system u' = L u exactly as the oracle's Shu-Osher
+    table of SSPRK(5,3) does (the folding of the residuals of u0 and u1 into
+    the register weights is exact algebra), and the stage times agree."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    n = 6
+    L = rng.normal(size=(n, n))
+    u0 = rng.normal(size=n)
+    dt = 0.07
+    regs = [u0.copy(), np.zeros(n), np.zeros(n), np.zeros(n)]
+    for cur, inputs, beta, out in sd.ssp53_stages():
+        regs[out] = sum(al * regs[k] for k, al in inputs) + beta * dt * (L @ regs[cur])
+    a, b, c = oracle.ssprk53_table()
+    U, R = [u0], []
+    for i in range(1, 6):
+        R.append(L @ U[-1])
+        U.append(sum(a[i, k] * U[k] + dt * b[i, k] * R[k] for k in range(i)))
+    assert np.abs(regs[0] - U[5]).max() <= 1e-14 * np.abs(U[5]).max()
+    np.testing.assert_allclose(sd.ssp53_stage_times(), c, rtol=0, atol=1e-15)
+    st = sd.ssp53_stages()
+    assert [s[0] for s in st] == [0, 1, 2, 3, 3] and [s[3] for s in st] == [1, 2, 3, 3, 0]
 
 
 @pytest.mark.parametrize("N_rho,L,kr", [(3.0, 0.0, 0.0), (3.0, 1e-6, 0.0), (5.0, 3e-7, 2e-6), (3.0, 8e-7, 5e-6)])
