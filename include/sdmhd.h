@@ -255,6 +255,25 @@ sdm_status sdm_ssprk53_stages(sdm_stage* out, double* c);
 sdm_status sdm_ssprk53_step(sdm_ctx* ctx, const sdm_params* prm, double* const* regs, double dt,
                             int traces_valid, void* ws, void* stream);
 
+/* sdm_ssprk53_step for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same five stages on regs[0..3] (device, caller-owned,
+ * [E][9][N3] FP64 each; regs[1..3] are overwritten), bitwise the same
+ * result, with no workspace argument.  The face traces the stages exchange
+ * live in a library-owned static device array of 64 MiB per device (held
+ * from the first sdm_create on that device until the process ends), so a
+ * mesh may need at most 64 MiB of them: E (6 (9 + 7) N^2) x 8 bytes in FP64,
+ * x 4 in FP32-mixed (2,427 elements at p = 5 in FP64, 4,854 in
+ * FP32-mixed); a larger mesh returns SDM_EINVAL with the limit in the
+ * message.  The first stage always recomputes the traces of regs[0] (no
+ * traces_valid).  Calls, no-allocation or not, allocate nothing, and this
+ * one frees nothing.  All contexts on one device share the one array:
+ * calls that may overlap on one device (different streams, or other
+ * threads) race and must be serialised by the caller; a call on one stream
+ * after another completes is safe. */
+sdm_status sdm_ssprk53_step_noalloc(sdm_ctx* ctx, const sdm_params* prm, double* const* regs, double dt,
+                                    void* stream);
+
 /* The two halves of sdm_rk_stage, for a mesh split over several GPUs: the
  * volume half (face traces of regs[cur] unless traces_valid, then every
  * element's residual except the neighbour half of the viscous flux; it

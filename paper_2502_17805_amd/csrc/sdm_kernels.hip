@@ -54,6 +54,14 @@ struct DevTab {
 __constant__ DevTab<double> c_tab_d[kNMax + 1];
 __constant__ DevTab<float> c_tab_f[kNMax + 1];
 
+// Scratch of the allocation-free SSPRK(5,3) step: the face traces of Q and of
+// the viscous normal flux that the stages exchange between face neighbours.
+// One copy per device, held until the process ends.  Host code never passes
+// this name to a kernel: it takes the device address from
+// hipGetSymbolAddress (sdm_create, once per device) and uses that.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 template <typename T>
 __device__ __forceinline__ const DevTab<T>& tab(int N);
 template <>
@@ -1329,6 +1337,24 @@ sdm_status upload_tables(int device) {
   return SDM_OK;
 }
 
+std::mutex g_scratch_mu;
+void* g_scratch_addr[64] = {nullptr};
+
+// Device address of `scratch` on `device` (which must be current): looked up
+// once per device; each device holds its own copy at its own address.
+sdm_status scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= 64) return fail(SDM_EINVAL, "device index out of range");
+  if (!g_scratch_addr[device]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(SDM_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_addr[device] = ptr;
+  }
+  *out = g_scratch_addr[device];
+  return SDM_OK;
+}
+
 Phys<double> to_phys(const sdm_params* p) {
   Phys<double> o;
   o.gamma = p->gamma;
@@ -1356,6 +1382,7 @@ Phys<double> to_phys(const sdm_params* p) {
 
 struct sdm_ctx {
   int device = 0;
+  void* scratch = nullptr;  // device address of this device's `scratch`
   int p = 5;
   int N = 6;
   int arith = 0;
@@ -1627,8 +1654,11 @@ sdm_status sdm_create(int device, int p, int arith, sdm_ctx** out) {
   HIP_TRY(hipSetDevice(device));
   sdm_status st = upload_tables(device);
   if (st != SDM_OK) return st;
+  void* scr = nullptr;
+  if ((st = scratch_address(device, &scr)) != SDM_OK) return st;
   sdm_ctx* c = new sdm_ctx;
   c->device = device;
+  c->scratch = scr;
   c->p = p;
   c->N = p + 1;
   c->arith = arith;
@@ -1779,6 +1809,7 @@ sdm_status stage_parts(sdm_ctx* c, const sdm_params* p, double* const* regs, int
   r.beta_dt = stg->beta * dt;
   r.write_traces = 1;
   r.fuse = 1;  // k_volume forms the stage output
+  r.Rp = nullptr;  // a stage never uses the partial-residual region
   Launch L = single(r);
   if (parts & 1) {
     if (!stg->traces_valid && (st = run(c, 0, L, s)) != SDM_OK) return st;
@@ -1836,6 +1867,32 @@ sdm_status sdm_ssprk53_step(sdm_ctx* c, const sdm_params* p, double* const* regs
   st[0].traces_valid = traces_valid ? 1 : 0;
   for (int i = 0; i < 5; ++i)
     if ((s = stage_parts(c, p, regs, 4, &st[i], dt, ws, stream, 3, "ssprk53_step")) != SDM_OK) return s;
+  return SDM_OK;
+}
+
+sdm_status sdm_ssprk53_step_noalloc(sdm_ctx* c, const sdm_params* p, double* const* regs, double dt,
+                                    void* stream) {
+  if (!c || !regs) return fail(SDM_EINVAL, "ssprk53_step_noalloc: NULL argument");
+  if (!c->bound) return fail(SDM_ESTATE, "ssprk53_step_noalloc: no mesh bound");
+  if (!c->scratch) return fail(SDM_ESTATE, "ssprk53_step_noalloc: no scratch address for this device");
+  size_t off[4];
+  ws_layout(c, off);
+  const size_t need = off[2];  // the two trace regions; a stage leaves the rest unused
+  if (need > kScratchBytes) {
+    const size_t per = need / (size_t)c->mesh.n_elem;
+    return fail(SDM_EINVAL, "ssprk53_step_noalloc: the mesh needs " + std::to_string(need) +
+                                " bytes of face-trace scratch, the maximum is " + std::to_string(kScratchBytes) +
+                                " (" + std::to_string(kScratchBytes / per) + " elements at this degree and arithmetic)");
+  }
+  sdm_stage st[5];
+  sdm_status s = sdm_ssprk53_stages(st, nullptr);
+  if (s != SDM_OK) return s;
+  // the scratch holds whatever the last call on this device left: the first
+  // stage always computes the traces of regs[0]
+  st[0].traces_valid = 0;
+  for (int i = 0; i < 5; ++i)
+    if ((s = stage_parts(c, p, regs, 4, &st[i], dt, c->scratch, stream, 3, "ssprk53_step_noalloc")) != SDM_OK)
+      return s;
   return SDM_OK;
 }
 

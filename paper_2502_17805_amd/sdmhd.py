@@ -11,6 +11,7 @@ Entry points mirror include/sdmhd.h:
   Solver.residual(prm, Q)          R = dQ/dt                 (sdm_residual)
   Solver.stage(prm, regs, st, dt)  one fused Shu-Osher stage (sdm_rk_stage)
   Solver.step(prm, dt)             one SSPRK(5,3) step     (sdm_ssprk53_step)
+  Solver.step_noalloc(prm, dt)     the same without a workspace (sdm_ssprk53_step_noalloc)
   Solver.diagnostics(prm, Q)       volume, mass, energy, KE, E_B, div B, ...
   sph_bins / Solver.sph_profiles   spherical-component sums per (r, theta) bin
   background_profile(r, ...)       polytrope / flux-balanced initial background
@@ -103,6 +104,7 @@ _lib.sdm_sph_profiles.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp, _vp]
 _lib.sdm_background_profile.argtypes = [C.POINTER(BackgroundDesc), C.c_int64, _vp, _vp, _vp, _vp]
 _lib.sdm_ssprk53_stages.argtypes = [C.POINTER(Stage), C.POINTER(C.c_double)]
 _lib.sdm_ssprk53_step.argtypes = [_vp, C.POINTER(Params), C.POINTER(C.c_void_p), C.c_double, C.c_int, _vp, _vp]
+_lib.sdm_ssprk53_step_noalloc.argtypes = [_vp, C.POINTER(Params), C.POINTER(C.c_void_p), C.c_double, _vp]
 _lib.sdm_batch_workspace_size.argtypes = [C.c_int, C.POINTER(C.c_size_t)]
 _lib.sdm_batch_stage.argtypes = [C.POINTER(BatchItem), C.c_int, _vp, C.c_size_t, C.c_int, _vp]
 _lib.sdm_profile_enable.argtypes = [_vp, C.c_int]
@@ -112,7 +114,7 @@ for _f in ("sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes", "sdm_box_build
            "sdm_rk_stage", "sdm_diagnostics", "sdm_profile_enable", "sdm_profile_read",
            "sdm_batch_workspace_size", "sdm_batch_stage", "sdm_workspace_traces", "sdm_rk_stage_volume",
            "sdm_rk_stage_finish", "sdm_sph_bins", "sdm_sph_profiles", "sdm_ssprk53_stages", "sdm_ssprk53_step",
-           "sdm_background_profile"):
+           "sdm_ssprk53_step_noalloc", "sdm_background_profile"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTED = ("sdm_last_error", "sdm_version", "sdm_shell_sizes", "sdm_shell_build", "sdm_box_sizes",
@@ -120,7 +122,8 @@ EXPORTED = ("sdm_last_error", "sdm_version", "sdm_shell_sizes", "sdm_shell_build
             "sdm_workspace_size", "sdm_residual", "sdm_rk_stage", "sdm_diagnostics",
             "sdm_profile_enable", "sdm_profile_read", "sdm_batch_workspace_size", "sdm_batch_stage",
             "sdm_workspace_traces", "sdm_rk_stage_volume", "sdm_rk_stage_finish", "sdm_sph_bins",
-            "sdm_sph_profiles", "sdm_ssprk53_stages", "sdm_ssprk53_step", "sdm_background_profile")
+            "sdm_sph_profiles", "sdm_ssprk53_stages", "sdm_ssprk53_step", "sdm_ssprk53_step_noalloc",
+            "sdm_background_profile")
 KERNELS = ("traces", "volume", "volume_diag", "finish_residual", "finish_stage")
 
 
@@ -439,6 +442,15 @@ class Solver:
         _check(_lib.sdm_ssprk53_step(self._h, C.byref(prm), arr, dt, 1 if self._traces_of == 0 else 0,
                                      self.ws.data_ptr(), self._stream()))
         self._traces_of = 0
+
+    def step_noalloc(self, prm: Params, dt: float, regs=None):
+        """One SSPRK(5,3) step of regs[0] with the library's static face-trace
+        scratch instead of the workspace (sdm_ssprk53_step_noalloc)."""
+        regs = self.regs if regs is None else regs
+        arr = (C.c_void_p * 4)(*[r.data_ptr() for r in regs[:4]])
+        _check(_lib.sdm_ssprk53_step_noalloc(self._h, C.byref(prm), arr, dt, self._stream()))
+        if regs is self.regs:
+            self._traces_of = None  # the workspace was not touched
 
     def profile(self, enable: bool):
         _check(_lib.sdm_profile_enable(self._h, 1 if enable else 0))
