@@ -10,8 +10,9 @@
  * named there.  Device work is hand-written HIP; every pointer marked
  * "device" must be device memory of the context's GPU, allocated and owned
  * by the caller (the library never frees it and allocates no device memory
- * except its static constant tables).  Calls that take a stream only enqueue
- * work on it; results are valid after the stream is synchronised.
+ * except its static constant tables and the static trace scratch of
+ * sdm_ssprk53_step_noalloc).  Calls that take a stream only enqueue work on
+ * it; results are valid after the stream is synchronised.
  *
  * Layouts (all row-major, last index fastest):
  *   N      = p + 1 solution points per direction; N3 = N^3; NF = (N+1) N^2
@@ -381,19 +382,30 @@ sdm_status sdm_sph_bins(int64_t n_elem, int p, const double* x_sp, double rb, do
 sdm_status sdm_sph_profiles(sdm_ctx* ctx, const double* Q, const int32_t* order, const int64_t* offsets,
                             int n_bins, double* out, void* stream);
 
-/* Bytes of DEVICE scratch sdm_batch_stage needs for n_items runs (their
- * descriptor tables). */
+/* Bytes of DEVICE scratch sdm_batch_stage needs for n_items runs (the work
+ * lists of the batch); 256-byte aligned. */
 sdm_status sdm_batch_workspace_size(int n_items, size_t* bytes);
 
-/* Serving: advance n_items independent runs by one fused RK stage each in
- * shared launches (trace pass for items without valid traces, one volume
- * pass, one finish pass) over the concatenated elements of all runs, one
- * workgroup per element; a pass with more than max_blocks elements (0: no
- * limit) is issued as consecutive launches of at most max_blocks
- * workgroups.  Every run gets exactly the arithmetic of sdm_rk_stage on its
- * own (results are bitwise identical alone and in a batch).  All items must
- * share p, arithmetic and device.  The descriptor table is staged through
- * library-owned pinned host memory and copied into batch_ws on `stream`. */
+/* Serving (continuous batching of independent runs; not part of the paper's
+ * method): advance n_items runs by one fused RK stage each (the stage of
+ * sdm_rk_stage, Sec. "Spectral Difference Method").  The runs may differ in
+ * mesh, degree and parameters; they must share the arithmetic and the
+ * device.  The library builds a device work list per degree: the runs'
+ * stage descriptors and element offsets, copied (staged through
+ * library-owned pinned host memory) into batch_ws on `stream`.  Each degree
+ * group then takes three launches over the concatenated elements of its
+ * runs, one workgroup per element (trace pass for items without valid
+ * traces, volume pass, finish pass); a pass with more than max_blocks
+ * elements (0: no limit) is issued as consecutive launches of at most
+ * max_blocks workgroups.  The first degree group runs on `stream`, the
+ * others on library-owned streams (default priority, created once per
+ * device) that start after the work-list copy and that `stream` waits for:
+ * the groups overlap on the device, and work enqueued on `stream`
+ * afterwards sees every run's stage done.  Every run gets exactly the
+ * arithmetic of sdm_rk_stage on its own: results are bitwise identical
+ * alone and in any batch.  batch_ws must not be reused by another call
+ * before this one's work on `stream` has been enqueued (the next call on
+ * the same stream is safe). */
 sdm_status sdm_batch_stage(const sdm_batch_item* items, int n_items, void* batch_ws,
                            size_t batch_ws_bytes, int max_blocks, void* stream);
 

@@ -73,6 +73,7 @@ __device__ __forceinline__ const DevTab<float>& tab<float>(int N) { return c_tab
 // per-run descriptor (kernel argument for one run, device array for batches)
 // ---------------------------------------------------------------------------
 struct RunDesc {
+  int32_t N;           // solution points per direction (p + 1)
   int64_t E;
   int64_t n_bfaces;
   const double* x_sp;
@@ -102,10 +103,13 @@ struct RunDesc {
   Phys<double> P;
 };
 
+// One launch: a single run (many == nullptr), or the work list of a batch of
+// runs of one degree: their descriptors and element offsets (prefix[k] =
+// elements of runs 0 .. k-1), one element per workgroup.
 struct Launch {
   RunDesc one;                  // used when many == nullptr
   const RunDesc* many;          // batched runs (device)
-  const int64_t* prefix;        // [n_run + 1] element offsets of the runs
+  const int64_t* prefix;        // [n_run + 1] element offsets of the runs (device)
   int32_t n_run;
   int64_t n_work;               // work items end here (one element each)
   int64_t w0;                   // first work item of this launch (one per workgroup)
@@ -189,8 +193,8 @@ __device__ __forceinline__ void fill_run(Run<T>& r, S& d) {
   r.P = cvt_phys<T>(d.P);
 }
 
-// the run and element of work item w (batched: last run whose element offset
-// is <= w, by binary search over the prefix table)
+// the run and element of work item w (batched: the last run whose element
+// offset is <= w, by binary search over the prefix table)
 template <typename T>
 __device__ __forceinline__ Run<T> view(const Launch& L, int64_t w) {
   Run<T> r;
@@ -461,44 +465,66 @@ __device__ __forceinline__ void load_outside(const Run<T>& R, int f, int ab, int
 // the wave) are staged once per workgroup in LDS: I [N+1][N], D [N][N+1]
 // ---------------------------------------------------------------------------
 template <int N, typename T>
-__device__ __forceinline__ void stage_tables(T* sI, T* sD, int is = 1, int ds = 1) {
+__device__ __forceinline__ void stage_tables(T* sI, T* sD, int tid, int nthreads) {
   const DevTab<T>& tb = tab<T>(N);
-  for (int i = threadIdx.x; i < (N + 1) * N; i += blockDim.x) {
-    sI[i * is] = tb.I[i / N][i % N];
-    sD[i * ds] = tb.D[i / (N + 1)][i % (N + 1)];
+  for (int i = tid; i < (N + 1) * N; i += nthreads) {
+    sI[i] = tb.I[i / N][i % N];
+    sD[i] = tb.D[i / (N + 1)][i % (N + 1)];
   }
 }
 
 // ---------------------------------------------------------------------------
+// LDS of one element, per pass: the kernels below take a base pointer into a
+// workgroup buffer, so that a single-element launch and a batched launch (one
+// buffer holding one element of degree 5 or several of a lower degree) run
+// the same code.  Offsets are 16-byte aligned.
+// ---------------------------------------------------------------------------
+constexpr size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
+
+template <int N, typename T>
+struct TraceLds {
+  static constexpr int N3 = N * N * N;
+  static constexpr size_t oQ = 0, oI = al16(oQ + sizeof(T) * 9 * N3), oD = al16(oI + sizeof(T) * (N + 1) * N);
+  static constexpr size_t bytes = al16(oD + sizeof(T) * N * (N + 1));
+};
+
+// ---------------------------------------------------------------------------
 // k_traces: face traces of Q (used before a run's first stage)
 // ---------------------------------------------------------------------------
+// tid: this thread's index within the element (>= the element's thread
+// count for threads without work, which still reach every barrier)
+template <int N, typename T>
+__device__ __forceinline__ void traces_body(const Run<T>& R, int tid, char* lds) {
+  constexpr int N2 = N * N, N3 = N2 * N, BS = block_threads<N>();
+  using Ly = TraceLds<N, T>;
+  T* sQ = reinterpret_cast<T*>(lds + Ly::oQ);
+  T* sI = reinterpret_cast<T*>(lds + Ly::oI);
+  T* sD = reinterpret_cast<T*>(lds + Ly::oD);
+  stage_tables<N>(sI, sD, tid, BS);
+  const GBL double* Qe = R.Q + R.e * 9 * N3;
+  for (int i = tid; i < 9 * N3; i += BS) sQ[i] = (T)Qe[i];
+  __syncthreads();
+  GBL T* tr = R.Qtr + R.e * 6 * 9 * N2;
+  for (int it = tid; it < 6 * 9 * N2; it += BS) {
+    const int ab = it % N2, fv = it / N2, v = fv % 9, f = fv / 9;
+    const int d = f >> 1;
+    const T* wI = sI + ((f & 1) ? N : 0) * N;
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) s += wI[i] * sQ[v * N3 + sp_line<N>(d, ab % N, ab / N, i)];
+    tr[it] = s;
+  }
+  __syncthreads();
+}
+
 template <int N, typename T>
 __global__ __launch_bounds__(block_threads<N>()) void k_traces(Launch L) {
-  constexpr int N2 = N * N, N3 = N2 * N, BS = block_threads<N>();
-  __shared__ T sQ[9 * N3];
-  __shared__ T sI[(N + 1) * N], sD[N * (N + 1)];
-  stage_tables<N>(sI, sD);
-  {
-    // one element per workgroup; no loop, so nothing per element is kept
-    // live across elements
-    const int64_t w = L.w0 + blockIdx.x;
-    if (w >= L.n_work) return;
-    const Run<T> R = view<T>(L, w);
-    const GBL double* Qe = R.Q + R.e * 9 * N3;
-    for (int i = threadIdx.x; i < 9 * N3; i += BS) sQ[i] = (T)Qe[i];
-    __syncthreads();
-    GBL T* tr = R.Qtr + R.e * 6 * 9 * N2;
-    for (int it = threadIdx.x; it < 6 * 9 * N2; it += BS) {
-      const int ab = it % N2, fv = it / N2, v = fv % 9, f = fv / 9;
-      const int d = f >> 1;
-      const T* wI = sI + ((f & 1) ? N : 0) * N;
-      T s = T(0);
-#pragma unroll
-      for (int i = 0; i < N; ++i) s += wI[i] * sQ[v * N3 + sp_line<N>(d, ab % N, ab / N, i)];
-      tr[it] = s;
-    }
-    __syncthreads();
-  }
+  __shared__ __align__(16) char lds[TraceLds<N, T>::bytes];
+  // one element per workgroup; no loop, so nothing per element is kept
+  // live across elements
+  const int64_t w = L.w0 + blockIdx.x;
+  if (w >= L.n_work) return;
+  traces_body<N, T>(view<T>(L, w), threadIdx.x, lds);
 }
 
 // divergence contribution of the interior flux points of family d (stored
@@ -612,47 +638,54 @@ constexpr int volume_waves() {
   return sizeof(T) == 8 ? SDM_VOLUME_WAVES_F64 : SDM_VOLUME_WAVES_F32;
 }
 
+template <int N, typename T>
+struct VolLds {
+  static constexpr int N2 = N * N, N3 = N2 * N, NI = N2 * (N - 1), BS = block_threads<N>();
+  static constexpr int UN = (9 * NI > 9 * 6 * N2) ? 9 * NI : 9 * 6 * N2;
+  static constexpr int RS = row_stride<T>();
+  // FP64 rows have two spare slots, where the basis tables live (I in slot
+  // 36, D in slot 37, DI after I where the rows leave room)
+  static constexpr bool PADTAB = RS >= 38;
+  static constexpr bool DIPAD = PADTAB && (N + 1) * N + N * N <= N3;
+  static constexpr size_t oR = 0;
+  static constexpr size_t oU = al16(oR + sizeof(T) * N3 * RS);
+  static constexpr size_t oRed = al16(oU + sizeof(T) * UN);
+  static constexpr size_t oI = al16(oRed + sizeof(double) * (BS / 64) * 10);
+  static constexpr size_t oD = al16(oI + (PADTAB ? 0 : sizeof(T) * (N + 1) * N));
+  static constexpr size_t oDI = al16(oD + (PADTAB ? 0 : sizeof(T) * N * (N + 1)));
+  static constexpr size_t oP = al16(oDI + (DIPAD ? 0 : sizeof(T) * N * N));
+  static constexpr size_t bytes = al16(oP + sizeof(Phys<T>));
+};
+
 template <int N, typename T, bool DIAG>
-__global__ __launch_bounds__(block_threads<N>()) __attribute__((amdgpu_waves_per_eu(volume_waves<T>())))
-void k_volume(Launch L) {
+__device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds) {
   constexpr int N2 = N * N, N3 = N2 * N, NP = N + 1, NF = NP * N2, BS = block_threads<N>();
   constexpr int NI = N2 * (N - 1);  // interior flux points of one family
-  constexpr int UN = (9 * NI > 9 * 6 * N2) ? 9 * NI : 9 * 6 * N2;
   // a thread keeps its own face point / interior flux points across phases
   // when one pass covers them all
   constexpr int FL = face_lanes<N>();
   constexpr bool FACE_REG = FL <= BS;
   constexpr bool INT_REG = NI <= BS;
-  // the element's point rows (Q, then grad_x Q); FP64 rows have two spare
-  // slots, where the basis tables live (I in slot 36, D in slot 37)
-  constexpr int RS = row_stride<T>();
-  constexpr bool PADTAB = RS >= 38;
+  using Ly = VolLds<N, T>;
+  constexpr int RS = Ly::RS;
+  constexpr bool PADTAB = Ly::PADTAB, DIPAD = Ly::DIPAD;
   static_assert(!PADTAB || (N + 1) * N <= N3, "tables fit the spare slots");
-  __shared__ __align__(16) T sR[N3 * RS];
-  __shared__ T sU[UN];  // face jumps (common value - own trace), then fluxes: 9 per point
-  __shared__ double sRed[BS / 64][10];
-  // DI (the derivative of the SP polynomial at the SPs) follows I in slot 36
-  // where the rows leave room
-  constexpr bool DIPAD = PADTAB && (N + 1) * N + N * N <= N3;
-  __shared__ T sIa[PADTAB ? 1 : (N + 1) * N], sDa[PADTAB ? 1 : N * (N + 1)], sDIa[DIPAD ? 1 : N * N];
-  T* const sI = PADTAB ? sR + 36 : sIa;
-  T* const sD = PADTAB ? sR + 37 : sDa;
-  T* const sDI = DIPAD ? sR + 36 + (N + 1) * N * RS : sDIa;
+  // the element's point rows (Q, then grad_x Q)
+  T* const sR = reinterpret_cast<T*>(lds + Ly::oR);
+  T* const sU = reinterpret_cast<T*>(lds + Ly::oU);  // face jumps (common value - own trace), then fluxes: 9 per point
+  double(*const sRed)[10] = reinterpret_cast<double(*)[10]>(lds + Ly::oRed);
+  T* const sI = PADTAB ? sR + 36 : reinterpret_cast<T*>(lds + Ly::oI);
+  T* const sD = PADTAB ? sR + 37 : reinterpret_cast<T*>(lds + Ly::oD);
+  T* const sDI = DIPAD ? sR + 36 + (N + 1) * N * RS : reinterpret_cast<T*>(lds + Ly::oDI);
   constexpr int is = PADTAB ? RS : 1, ds = PADTAB ? RS : 1, dis = DIPAD ? RS : 1;
   // the physical parameters, read from LDS where they are used: held in
   // scalar registers for the whole element they overflow them
-  __shared__ Phys<T> sP;
+  Phys<T>& sP = *reinterpret_cast<Phys<T>*>(lds + Ly::oP);
   static_assert(BS >= N3, "one solution point per thread");
   const DevTab<T>& tb = tab<T>(N);
-  const int tid = threadIdx.x;
   const int ia0 = tid % N, ia1 = (tid / N) % N, ia2 = tid / N2;  // this thread's SP (tid < N3)
 
   {
-    // one element per workgroup; no loop, so nothing per element is kept
-    // live across elements
-    const int64_t w = L.w0 + blockIdx.x;
-    if (w >= L.n_work) return;
-    const Run<T> R = view<T>(L, w);
     const int64_t e = R.e;
     if (tid == 0) sP = R.P;
     const Phys<T>& P = sP;  // valid after the barrier that ends phase A
@@ -898,7 +931,7 @@ void k_volume(Launch L) {
           const double y = __shfl_down(x, off, 64);
           x = (k == 5 || k == 7 || k == 8) ? fmax(x, y) : x + y;
         }
-        if ((tid & 63) == 0) sRed[tid >> 6][k] = x;
+        if ((tid & 63) == 0 && tid < BS) sRed[tid >> 6][k] = x;
       }
       __syncthreads();
       if (tid == 0) {
@@ -1054,6 +1087,17 @@ void k_volume(Launch L) {
   }
 }
 
+template <int N, typename T, bool DIAG>
+__global__ __launch_bounds__(block_threads<N>()) __attribute__((amdgpu_waves_per_eu(volume_waves<T>())))
+void k_volume(Launch L) {
+  __shared__ __align__(16) char lds[VolLds<N, T>::bytes];
+  // one element per workgroup; no loop, so nothing per element is kept
+  // live across elements
+  const int64_t w = L.w0 + blockIdx.x;
+  if (w >= L.n_work) return;
+  volume_body<N, T, DIAG>(view<T>(L, w), threadIdx.x, lds);
+}
+
 // the neighbour's viscous normal flux at face point `it` (face it / N^2) of
 // element e: its stored flux (orientation-mapped) or, on an import face, the
 // caller's; zero on walls and Dirichlet faces (completed in k_volume)
@@ -1087,19 +1131,24 @@ __device__ __forceinline__ void gather_vflux(const Run<T>& R, const GBL int32_t*
 // k_finish: neighbour half of the viscous common flux, then R or the stage
 // ---------------------------------------------------------------------------
 template <int N, typename T, bool STAGE>
-__global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
+struct FinLds {
+  static constexpr int N2 = N * N, N3 = N2 * N;
+  static constexpr size_t oV = 0, oOut = al16(oV + sizeof(T) * 6 * 7 * N2);
+  static constexpr size_t oI = al16(oOut + sizeof(double) * (STAGE ? 9 * N3 : 1));
+  static constexpr size_t oD = al16(oI + sizeof(T) * (N + 1) * N);
+  static constexpr size_t bytes = al16(oD + sizeof(T) * N * (N + 1));
+};
+
+template <int N, typename T, bool STAGE>
+__device__ __forceinline__ void finish_body(const Run<T>& R, int tid, char* lds) {
   constexpr int N2 = N * N, N3 = N2 * N, NP = N + 1, BS = block_threads<N>();
   static_assert(BS >= N3, "one solution point per thread");
-  __shared__ T sV[6 * 7 * N2];
-  __shared__ double sOut[STAGE ? 9 * N3 : 1];
-  __shared__ T sI[(N + 1) * N], sD[N * (N + 1)];
-  const int tid = threadIdx.x;
+  using Ly = FinLds<N, T, STAGE>;
+  T* const sV = reinterpret_cast<T*>(lds + Ly::oV);
+  double* const sOut = reinterpret_cast<double*>(lds + Ly::oOut);
+  T* const sI = reinterpret_cast<T*>(lds + Ly::oI);
+  T* const sD = reinterpret_cast<T*>(lds + Ly::oD);
   {
-    // one element per workgroup; no loop, so nothing per element is kept
-    // live across elements
-    const int64_t w = L.w0 + blockIdx.x;
-    if (w >= L.n_work) return;
-    const Run<T> R = view<T>(L, w);
     const int64_t e = R.e;
     const GBL int32_t* nb6 = R.nbr + e * 6;
     // the neighbours' viscous normal fluxes on the six faces: with one face
@@ -1139,7 +1188,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
         for (int c = 0; c < 7; ++c) sV[((it / N2) * 7 + c) * N2 + it % N2] = fv[c];
       }
     }
-    stage_tables<N>(sI, sD);
+    stage_tables<N>(sI, sD, tid, BS);
     __syncthreads();
     if (sp < N3) {
       ji = recip(ji);
@@ -1188,6 +1237,16 @@ __global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
       }
     }
   }
+}
+
+template <int N, typename T, bool STAGE>
+__global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
+  __shared__ __align__(16) char lds[FinLds<N, T, STAGE>::bytes];
+  // one element per workgroup; no loop, so nothing per element is kept
+  // live across elements
+  const int64_t w = L.w0 + blockIdx.x;
+  if (w >= L.n_work) return;
+  finish_body<N, T, STAGE>(view<T>(L, w), threadIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1437,6 +1496,7 @@ RunDesc make_desc(const sdm_ctx* c, const sdm_params* p, const double* Q, void* 
   std::memset(&r, 0, sizeof r);
   size_t off[4];
   ws_layout(c, off);
+  r.N = c->N;
   r.E = c->mesh.n_elem;
   r.n_bfaces = c->mesh.n_bfaces;
   r.x_sp = c->mesh.x_sp;
@@ -1574,8 +1634,37 @@ sdm_status stage_copy(const void* src, size_t bytes, void* dst_dev, hipStream_t 
   return SDM_OK;
 }
 
-size_t batch_table_bytes(int n) { return align256(sizeof(RunDesc) * (size_t)n) + align256(sizeof(int64_t) * (n + 1)); }
+// Batch workspace: the work lists of the batch, one per pass kind, each
+// with the runs of every degree group stored contiguously (descriptors, then
+// element offsets with one extra entry per group): [runs | offsets] for the
+// volume and finish passes, then the same for the runs whose traces must be
+// computed first.  At most kBatchGroups degrees (N = 2 .. 7).
+constexpr int kBatchGroups = 6;
+size_t batch_list_bytes(int n) {
+  return align256(sizeof(RunDesc) * (size_t)n) + align256(sizeof(int64_t) * (size_t)(n + kBatchGroups));
+}
+size_t batch_ws_bytes(int n) { return 2 * batch_list_bytes(n); }
 
+// Library-owned streams and events of one device for the degree groups of a
+// batch after the first (default priority; created once, kept until exit).
+struct BatchStreams {
+  hipStream_t side[kBatchGroups] = {};
+  hipEvent_t fork = nullptr, join[kBatchGroups] = {};
+};
+std::mutex g_bs_mu;
+BatchStreams g_bs[64];
+
+sdm_status batch_streams(int device, int n_side, BatchStreams** out) {
+  std::lock_guard<std::mutex> lk(g_bs_mu);
+  BatchStreams& b = g_bs[device];
+  if (!b.fork) HIP_TRY(hipEventCreateWithFlags(&b.fork, hipEventDisableTiming));
+  for (int k = 0; k < n_side; ++k) {
+    if (!b.side[k]) HIP_TRY(hipStreamCreateWithFlags(&b.side[k], hipStreamNonBlocking));
+    if (!b.join[k]) HIP_TRY(hipEventCreateWithFlags(&b.join[k], hipEventDisableTiming));
+  }
+  *out = &b;
+  return SDM_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -1949,26 +2038,27 @@ sdm_status sdm_sph_profiles(sdm_ctx* c, const double* Q, const int32_t* order, c
 
 sdm_status sdm_batch_workspace_size(int n_items, size_t* bytes) {
   if (n_items < 1 || !bytes) return fail(SDM_EINVAL, "batch_workspace_size: n_items >= 1 and bytes required");
-  *bytes = 2 * batch_table_bytes(n_items);
+  *bytes = batch_ws_bytes(n_items);
   return SDM_OK;
 }
 
-sdm_status sdm_batch_stage(const sdm_batch_item* items, int n_items, void* batch_ws, size_t batch_ws_bytes,
+sdm_status sdm_batch_stage(const sdm_batch_item* items, int n_items, void* batch_ws, size_t ws_bytes,
                            int max_blocks, void* stream) {
   if (!items || n_items < 1 || !batch_ws) return fail(SDM_EINVAL, "batch_stage: NULL argument or no items");
-  size_t need = 0;
-  sdm_batch_workspace_size(n_items, &need);
-  if (batch_ws_bytes < need) return fail(SDM_EINVAL, "batch_stage: batch workspace too small");
+  if (ws_bytes < batch_ws_bytes(n_items)) return fail(SDM_EINVAL, "batch_stage: batch workspace too small");
+  if ((uintptr_t)batch_ws % 256 != 0) return fail(SDM_EINVAL, "batch_stage: batch workspace not 256-byte aligned");
   sdm_ctx* c0 = items[0].ctx;
   if (!c0) return fail(SDM_EINVAL, "batch_stage: NULL context");
-  std::vector<RunDesc> all, tr;
-  std::vector<int64_t> pre_all{0}, pre_tr{0};
+  // the stage descriptor of every item, grouped by degree (groups in order
+  // of first appearance, items in their given order within a group)
+  std::vector<int> degrees;
+  std::vector<std::vector<RunDesc>> all(kBatchGroups), tr(kBatchGroups);
   for (int k = 0; k < n_items; ++k) {
     const sdm_batch_item& it = items[k];
     sdm_ctx* c = it.ctx;
     if (!c || !c->bound) return fail(SDM_ESTATE, "batch_stage: item without a bound mesh");
-    if (c->N != c0->N || c->arith != c0->arith || c->device != c0->device)
-      return fail(SDM_EINVAL, "batch_stage: items must share p, arithmetic and device");
+    if (c->arith != c0->arith || c->device != c0->device)
+      return fail(SDM_EINVAL, "batch_stage: items must share the arithmetic and the device");
     if (!it.regs || !it.ws || it.n_regs < 1 || it.n_regs > 16) return fail(SDM_EINVAL, "batch_stage: bad registers");
     const sdm_stage& st = it.stage;
     if (st.n_in < 0 || st.n_in > 4) return fail(SDM_EINVAL, "batch_stage: 0 <= n_in <= 4");
@@ -1988,46 +2078,75 @@ sdm_status sdm_batch_stage(const sdm_batch_item* items, int n_items, void* batch
     r.beta_dt = st.beta * it.dt;
     r.write_traces = 1;
     r.fuse = 1;
-    all.push_back(r);
-    pre_all.push_back(pre_all.back() + r.E);
-    if (!st.traces_valid) {
-      tr.push_back(r);
-      pre_tr.push_back(pre_tr.back() + r.E);
-    }
+    r.Rp = nullptr;  // a stage never uses the partial-residual region
+    size_t g = std::find(degrees.begin(), degrees.end(), c->N) - degrees.begin();
+    if (g == degrees.size()) degrees.push_back(c->N);
+    all[g].push_back(r);
+    if (!st.traces_valid) tr[g].push_back(r);
   }
+  const int G = (int)degrees.size();
   HIP_TRY(hipSetDevice(c0->device));
   hipStream_t s = (hipStream_t)stream;
-  // device tables: [descs | prefix] for all items, then the same for the
-  // items whose traces must be computed first
-  char* base = (char*)batch_ws;
-  const size_t tb_all = batch_table_bytes(n_items);
-  std::vector<char> host(2 * tb_all, 0);
-  auto pack = [&](size_t off, const std::vector<RunDesc>& d, const std::vector<int64_t>& pre) {
-    std::memcpy(host.data() + off, d.data(), sizeof(RunDesc) * d.size());
-    std::memcpy(host.data() + off + align256(sizeof(RunDesc) * (size_t)n_items), pre.data(), sizeof(int64_t) * pre.size());
+  // one host image of both work lists, one copy
+  const size_t lb = batch_list_bytes(n_items);
+  const size_t pre_off = align256(sizeof(RunDesc) * (size_t)n_items);
+  std::vector<char> host(batch_ws_bytes(n_items), 0);
+  struct Span { size_t run0, pre0; int n; int64_t E; };
+  std::vector<Span> sp_all(G), sp_tr(G);
+  auto pack = [&](size_t off, const std::vector<std::vector<RunDesc>>& lists, std::vector<Span>& spans) {
+    size_t run0 = 0;
+    for (int g = 0; g < G; ++g) {
+      const std::vector<RunDesc>& d = lists[g];
+      std::vector<int64_t> pre{0};
+      for (const RunDesc& r : d) pre.push_back(pre.back() + r.E);
+      std::memcpy(host.data() + off + sizeof(RunDesc) * run0, d.data(), sizeof(RunDesc) * d.size());
+      std::memcpy(host.data() + off + pre_off + sizeof(int64_t) * (run0 + g), pre.data(), sizeof(int64_t) * pre.size());
+      spans[g] = Span{run0, run0 + g, (int)d.size(), pre.back()};
+      run0 += d.size();
+    }
   };
-  pack(0, all, pre_all);
-  if (!tr.empty()) pack(tb_all, tr, pre_tr);
-  sdm_status st = stage_copy(host.data(), tr.empty() ? tb_all : 2 * tb_all, base, s);
+  pack(0, all, sp_all);
+  pack(lb, tr, sp_tr);
+  sdm_status st = stage_copy(host.data(), host.size(), batch_ws, s);
   if (st != SDM_OK) return st;
-  auto launch_for = [&](size_t off, int n_run, int64_t n_work) {
-    Launch L;
-    std::memset(&L, 0, sizeof L);
-    L.many = (const RunDesc*)(base + off);
-    L.prefix = (const int64_t*)(base + off + align256(sizeof(RunDesc) * (size_t)n_items));
-    L.n_run = n_run;
-    L.n_work = n_work;
-    return L;
-  };
-  const int64_t cap = max_blocks > 0 ? max_blocks : ((int64_t)1 << 30);
-  if (!tr.empty()) {
-    Launch Lt = launch_for(tb_all, (int)tr.size(), pre_tr.back());
-    Lt.n_work = pre_tr.back();
-    if ((st = run_capped(c0, 0, Lt, s, cap)) != SDM_OK) return st;
+  // the first degree group runs on the caller's stream, the others on
+  // library streams that wait for the table copy; the caller's stream then
+  // waits for them, so work of different degrees overlaps on the device
+  BatchStreams* bs = nullptr;
+  if (G > 1) {
+    if ((st = batch_streams(c0->device, G - 1, &bs)) != SDM_OK) return st;
+    HIP_TRY(hipEventRecord(bs->fork, s));
   }
-  Launch La = launch_for(0, n_items, pre_all.back());
-  if ((st = run_capped(c0, 1, La, s, cap)) != SDM_OK) return st;
-  return run_capped(c0, 4, La, s, cap);
+  char* base = (char*)batch_ws;
+  const int64_t cap = max_blocks > 0 ? max_blocks : ((int64_t)1 << 30);
+  for (int g = 0; g < G; ++g) {
+    hipStream_t sg = g == 0 ? s : bs->side[g - 1];
+    if (g > 0) HIP_TRY(hipStreamWaitEvent(sg, bs->fork, 0));
+    auto launch_of = [&](size_t off, const Span& sp) {
+      Launch L;
+      std::memset(&L, 0, sizeof L);
+      L.one.N = degrees[g];
+      L.many = (const RunDesc*)(base + off + sizeof(RunDesc) * sp.run0);
+      L.prefix = (const int64_t*)(base + off + pre_off + sizeof(int64_t) * sp.pre0);
+      L.n_run = sp.n;
+      L.n_work = sp.E;
+      return L;
+    };
+    auto go = [&](int which, const Launch& L) -> sdm_status {
+      const hipError_t e = c0->arith ? dispatch_N<float>(degrees[g], which, L, sg, cap)
+                                     : dispatch_N<double>(degrees[g], which, L, sg, cap);
+      return e == hipSuccess ? SDM_OK : fail(SDM_EHIP, std::string("batch kernel launch: ") + hipGetErrorString(e));
+    };
+    if (sp_tr[g].n > 0 && (st = go(0, launch_of(lb, sp_tr[g]))) != SDM_OK) return st;
+    const Launch La = launch_of(0, sp_all[g]);
+    if ((st = go(1, La)) != SDM_OK) return st;
+    if ((st = go(4, La)) != SDM_OK) return st;
+    if (g > 0) {
+      HIP_TRY(hipEventRecord(bs->join[g - 1], sg));
+      HIP_TRY(hipStreamWaitEvent(s, bs->join[g - 1], 0));
+    }
+  }
+  return SDM_OK;
 }
 
 }  // extern "C"

@@ -4,13 +4,17 @@ Requests (shell size, polynomial degree, density scale heights, seed, number of
 SSPRK(5,3) steps, arithmetic) arrive over time.  A request is admitted as soon
 as a slot is free and its device memory fits the HBM budget; its mesh, state
 registers and workspace then stay resident on the device until it finishes.
-Every scheduler iteration advances each active run by one SSPRK(5,3) step:
-for each of the five stages, the stages of all active runs with the same
-degree and arithmetic go into one shared launch sequence (sdm_batch_stage:
-a grid-stride loop over the concatenated elements of all runs), so runs that
-arrive while others are on the GPU join the same launches.  A run's arithmetic
-is exactly that of a single-run stage, so its result is bitwise the same alone
-and in any mix.
+Every scheduler iteration enqueues one SSPRK(5,3) step of each active run:
+for each of the five stages, the stages of all active runs of one arithmetic
+go into one sdm_batch_stage call, whose work lists cover every degree (the
+degree groups of one call overlap on the device), so runs that arrive while
+others are on the GPU join the same launches.  The host does not wait for
+the GPU after each step: it stays at most `ahead` steps in front (events),
+and learns that a run has finished, or has gone non-finite, by polling the
+event after its diagnostics, which are copied to pinned host memory
+asynchronously.  A run whose periodic diagnostics report NaN/Inf is evicted
+(its result carries the flag).  A run's arithmetic is exactly that of a
+single-run stage, so its result is bitwise the same alone and in any mix.
 """
 from __future__ import annotations
 
@@ -146,6 +150,27 @@ class _Run:
         self.steps_done = 0
         self.traces_valid = False
         self.bytes = request_bytes(req)
+        # host side of the run's asynchronous diagnostics (pinned) and the
+        # event after which they are valid
+        self.diag_dev = torch.zeros(16, dtype=torch.float64, device=device)
+        self.diag_host = torch.zeros(16, dtype=torch.float64).pin_memory()
+        self.diag_event = None
+        self.state_host = None
+
+    def enqueue_diagnostics(self, stream, keep_state=False):
+        """Diagnostics of register 0 into pinned host memory after the work
+        enqueued so far; returns the event after which they are valid."""
+        import torch
+        sd._check(sd._lib.sdm_diagnostics(self.ctx, C.byref(self.prm), self.regs[0].data_ptr(),
+                                          self.diag_dev.data_ptr(), self.ws.data_ptr(), stream))
+        self.diag_host.copy_(self.diag_dev, non_blocking=True)
+        if keep_state:
+            self.state_host = torch.empty(self.regs[0].shape, dtype=torch.float64).pin_memory()
+            self.state_host.copy_(self.regs[0], non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record()
+        self.diag_event = ev
+        return ev
 
     def item(self, cur, inputs, beta, out):
         st = sd.Stage()
@@ -164,16 +189,19 @@ class _Run:
 
 
 class Server:
-    """Admission by slots and HBM budget; one batched SSPRK step per iteration."""
+    """Admission by slots and HBM budget; one batched SSPRK step per iteration,
+    enqueued without waiting for the GPU."""
 
     def __init__(self, budget_bytes: float = 200e9, max_slots: int = 64, device: int = 0, max_blocks: int = 0,
-                 keep_states=False, max_elements: int = 0):
+                 keep_states=False, max_elements: int = 0, ahead: int = 2, check_every: int = 50):
         """keep_states: True (all), a set of request ids, or False: whose
         final states are copied back with their results.  max_elements > 0
         caps the elements resident at once (admission waits while the cap
         would be exceeded, except for a request that is alone): enough
         elements keep every CU busy, more only lengthen every resident
-        request's latency."""
+        request's latency.  ahead: steps the host may enqueue before the GPU
+        has finished them.  check_every: steps between a run's NaN checks
+        (0: only at the end)."""
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -182,6 +210,8 @@ class Server:
         self.max_elements = max_elements
         self.max_blocks = max_blocks
         self.keep_states = keep_states
+        self.ahead = max(1, ahead)
+        self.check_every = check_every
         self.cache = _MeshCache(self.device)
         nb = C.c_size_t()
         sd._check(sd._lib.sdm_batch_workspace_size(max_slots, C.byref(nb)))
@@ -193,9 +223,11 @@ class Server:
         return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
 
     def _step_all(self, active):
+        """Enqueue one SSPRK(5,3) step of every active run: per stage one
+        batch call per arithmetic, over runs of any degree."""
         groups = collections.defaultdict(list)
         for r in active:
-            groups[(r.req.p, r.req.arith)].append(r)
+            groups[r.req.arith].append(r)
         stages = sd.ssp53_stages()
         for cur, inputs, beta, out in stages:
             for runs in groups.values():
@@ -205,28 +237,36 @@ class Server:
         for r in active:
             r.steps_done += 1
 
-    def run(self, requests, prepare_inputs: bool = True):
+    def run(self, requests, prepare_inputs: bool = True, inputs=None):
         """Serve the requests (arrival times relative to the start).  With
         prepare_inputs the requests' inputs and meshes are made on the host
-        before the clock starts, so the latencies measure the GPU service."""
+        before the clock starts, so the latencies measure the GPU service.
+        inputs: {rid: (Q, params dict, dt)} given instead of the seeded ones."""
         torch = self.torch
         pending = collections.deque(sorted(requests, key=lambda q: q.arrival))
-        prepared = {}
+        prepared = dict(inputs or {})
         if prepare_inputs:
             for q in pending:
-                m = self.cache.host_mesh(q.Nz, q.Nr, q.p)
-                prepared[q.rid] = prepare(q, m)
-        active, results = [], []
-        used, peak_used, peak_active, iters, queued_wait = 0, 0, 0, 0, 0
+                if q.rid not in prepared:
+                    prepared[q.rid] = prepare(q, self.cache.host_mesh(q.Nz, q.Nr, q.p))
+        active, draining, results = [], [], []
+        inflight = collections.deque()  # events of the steps enqueued and not yet waited for
+        used, peak_used, peak_active, iters, queued_wait, evicted = 0, 0, 0, 0, 0, 0
+        stream = self._stream()
         torch.cuda.synchronize(self.device)
         t0 = time.perf_counter()
-        while pending or active:
+
+        def keep(r):
+            return self.keep_states is True or (self.keep_states and r.req.rid in self.keep_states)
+
+        while pending or active or draining:
             now = time.perf_counter() - t0
-            while pending and pending[0].arrival <= now and len(active) < self.max_slots:
+            while pending and pending[0].arrival <= now and len(active) + len(draining) < self.max_slots:
                 q = pending[0]
                 E_q = 6 * q.Nz * q.Nz * q.Nr
-                over_elems = self.max_elements > 0 and active and \
-                    sum(6 * r.req.Nz * r.req.Nz * r.req.Nr for r in active) + E_q > self.max_elements
+                resident = active + draining
+                over_elems = self.max_elements > 0 and resident and \
+                    sum(6 * r.req.Nz * r.req.Nz * r.req.Nr for r in resident) + E_q > self.max_elements
                 if used + request_bytes(q) > self.budget or over_elems:
                     queued_wait += 1
                     break
@@ -235,30 +275,51 @@ class Server:
                 used += r.bytes
                 active.append(r)
             peak_used = max(peak_used, used)
-            peak_active = max(peak_active, len(active))
-            if not active:
-                if pending:
-                    time.sleep(max(0.0, min(0.002, pending[0].arrival - (time.perf_counter() - t0))))
-                continue
-            self._step_all(active)
-            iters += 1
-            torch.cuda.synchronize(self.device)
-            tnow = time.perf_counter() - t0
+            peak_active = max(peak_active, len(active) + len(draining))
+            # runs whose last diagnostics have arrived: done (or evicted)
             still = []
-            for r in active:
-                if r.steps_done >= r.req.steps:
-                    out = torch.zeros(16, dtype=torch.float64, device=self.device)
-                    sd._check(sd._lib.sdm_diagnostics(r.ctx, C.byref(r.prm), r.regs[0].data_ptr(), out.data_ptr(),
-                                                      r.ws.data_ptr(), self._stream()))
-                    diag = out.cpu().numpy()
-                    keep = self.keep_states is True or (self.keep_states and r.req.rid in self.keep_states)
-                    state = r.regs[0].cpu().numpy() if keep else None
+            for r in draining:
+                if r.diag_event.query():
+                    tnow = time.perf_counter() - t0
+                    st = r.state_host.numpy().copy() if r.state_host is not None else None
                     results.append(Result(r.req.rid, r.req.arrival, r.t_admit, tnow, r.steps_done, r.req.dof,
-                                          diag, state))
+                                          r.diag_host.numpy().copy(), st))
                     used -= r.bytes
                     r.close(self.cache)
                 else:
                     still.append(r)
+            draining = still
+            # periodic NaN checks whose diagnostics have arrived
+            for r in list(active):
+                if r.diag_event is not None and r.diag_event.query():
+                    if r.diag_host[8].item() != 0.0:
+                        active.remove(r)
+                        evicted += 1
+                        r.enqueue_diagnostics(stream, keep(r))
+                        draining.append(r)
+                    r.diag_event = None if r in active else r.diag_event
+            if not active:
+                if draining:
+                    time.sleep(0.0002)
+                elif pending:
+                    time.sleep(max(0.0, min(0.002, pending[0].arrival - (time.perf_counter() - t0))))
+                continue
+            self._step_all(active)
+            iters += 1
+            ev = torch.cuda.Event()
+            ev.record()
+            inflight.append(ev)
+            if len(inflight) > self.ahead:
+                inflight.popleft().synchronize()
+            still = []
+            for r in active:
+                if r.steps_done >= r.req.steps:
+                    r.enqueue_diagnostics(stream, keep(r))
+                    draining.append(r)
+                    continue
+                if self.check_every and r.steps_done % self.check_every == 0 and r.diag_event is None:
+                    r.enqueue_diagnostics(stream)
+                still.append(r)
             active = still
         makespan = time.perf_counter() - t0
         lat = np.array([x.latency for x in results])
@@ -267,7 +328,8 @@ class Server:
                           p50_latency_s=float(np.percentile(lat, 50)) if len(lat) else None,
                           p99_latency_s=float(np.percentile(lat, 99)) if len(lat) else None,
                           dof_stage_per_s=work / makespan if makespan > 0 else None,
-                          peak_active=peak_active, peak_bytes=peak_used, admissions_deferred=queued_wait)
+                          peak_active=peak_active, peak_bytes=peak_used, admissions_deferred=queued_wait,
+                          evicted=evicted)
         return sorted(results, key=lambda x: x.rid), self.stats
 
 

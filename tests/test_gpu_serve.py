@@ -1,6 +1,8 @@
 """Served ensembles: each run's result is bitwise the same alone, in a mix
-of runs of different shell sizes and degrees, under forced queueing by a small
-HBM budget, and through the single-run stage API."""
+of runs of different shell sizes and degrees (one batch call per stage over
+all degrees), under forced queueing by a small HBM budget, and through the
+single-run stage API; a run that goes non-finite is evicted; batched stages
+match the oracle."""
 import numpy as np
 import pytest
 
@@ -118,50 +120,93 @@ def test_nan_run_does_not_touch_its_batch_neighbours(srv):
     assert torch.isfinite(alone.state).all() and not torch.isfinite(bad.state).all()
 
 
-def test_batch_rejects_mixed_degrees(srv):
+def test_mixed_degree_batch_equals_alone(srv):
+    """Runs of degree 3 and 5 (and two shell sizes) advanced together by
+    sdm_batch_stage, whose degree groups overlap on the device: each run is
+    bitwise what it is when batched alone."""
     import ctypes as C
 
     import torch
 
     from paper_2502_17805_amd import sdmhd as sd
-    a, b = sd.Solver(sd.shell(2, 1, 3)), sd.Solver(sd.shell(2, 1, 5))
-    nb = C.c_size_t()
-    sd._check(sd._lib.sdm_batch_workspace_size(2, C.byref(nb)))
-    bws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
-    prm = sd.make_params(c_h=1.0)
-    st = sd.Stage()
-    st.n_in, st.in_idx[0], st.alpha[0], st.cur, st.out, st.beta = 1, 0, 1.0, 0, 1, 0.5
-    items = (sd.BatchItem * 2)()
-    for k, s in enumerate((a, b)):
-        regs = (C.c_void_p * 4)(*[r.data_ptr() for r in s.regs])
-        items[k] = sd.BatchItem(s._h.value, C.pointer(prm), regs, 4, st, 1e-3, s.ws.data_ptr())
-    rc = sd._lib.sdm_batch_stage(items, 2, bws.data_ptr(), nb.value, 0,
-                                 C.c_void_p(torch.cuda.current_stream().cuda_stream))
-    assert rc != sd.SDM_OK and b"share p" in sd._lib.sdm_last_error()
-
-
-def test_batched_stages_match_oracle(srv, oracle):
-    """Two runs of different shell sizes and backgrounds advanced together
-    by sdm_batch_stage (one launch sequence per stage over both runs'
-    elements): each run's state after two SSPRK(5,3) steps against the FP64
-    oracle's, within 1e-12 of max|u_v| + dt T_v."""
-    import torch
-
-    from paper_2502_17805_amd import sdmhd as sd
-    runs = []
-    for (Nz, Nr, N_rho, seed) in ((2, 1, 3.0, 1000), (2, 2, 5.0, 1001)):
-        m = sd.shell(Nz, Nr, 5)
-        mo = oracle.Mesh.shell(6, Nz, Nr)
+    specs = ((2, 1, 3, 3.0, 11), (2, 2, 5, 5.0, 12), (3, 1, 3, 5.0, 13), (2, 1, 5, 3.0, 14))
+    made = []
+    for Nz, Nr, p, N_rho, seed in specs:
+        m = sd.shell(Nz, Nr, p)
         bg = inp.Background(N_rho)
         Q = inp.shell_state(m.x_sp, bg, seed)
         pr = inp.run_params(seed, bg)
         ch = inp.glm_speed(Q)
         pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
+        made.append((m, Q, sd.make_params(**pr), inp.time_step(Q, m.Sj_sp, ch, 0.1)))
+    dt = min(x[3] for x in made)
+    nb = C.c_size_t()
+    sd._check(sd._lib.sdm_batch_workspace_size(len(made), C.byref(nb)))
+    bws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    mixed = []
+    for m, Q, _, _ in made:
         s = sd.Solver(m)
+        s.set_state(Q)
+        mixed.append(s)
+    print(f"mixed-degree batch: {[x[:3] for x in specs]} dt={dt:.3e}", flush=True)
+    for _ in range(3):
+        _batch_step(sd, mixed, [x[2] for x in made], dt, bws, int(nb.value), stream)
+    for k, (m, Q, prm, _) in enumerate(made):
+        alone = sd.Solver(m)
+        alone.set_state(Q)
+        for _ in range(3):
+            _batch_step(sd, [alone], [prm], dt, bws, int(nb.value), stream)
+        torch.cuda.synchronize()
+        assert torch.isfinite(alone.state).all()
+        assert torch.equal(alone.state, mixed[k].state), specs[k]
+
+
+def test_nan_run_is_evicted(srv):
+    """A request whose input holds a NaN is evicted on its diagnostics flag
+    before its last step; the healthy requests served beside it are bitwise
+    what they are alone."""
+    import dataclasses
+
+    from paper_2502_17805_amd import sdmhd as sd
+    reqs = [srv.Request(0, 2, 1, 5, 3.0, 2000, 40, 0, 0.0), srv.Request(1, 2, 1, 3, 5.0, 2001, 40, 0, 0.0),
+            srv.Request(2, 2, 2, 5, 3.0, 2002, 40, 0, 0.0)]
+    bad = reqs[1]
+    m = sd.shell(bad.Nz, bad.Nr, bad.p)
+    Q, pr, dt = srv.prepare(bad, m)
+    Q = Q.copy()
+    Q[3, 4, 7] = np.nan
+    res, st = srv.Server(max_slots=4, keep_states=True, check_every=5).run(reqs, inputs={1: (Q, pr, dt)})
+    assert st["evicted"] == 1
+    assert res[1].diag[8] == 1.0 and res[1].steps < bad.steps
+    for q in (reqs[0], reqs[2]):
+        alone, _ = srv.Server(max_slots=1, keep_states=True).run([dataclasses.replace(q, arrival=0.0)])
+        assert res[q.rid].diag[8] == 0.0 and res[q.rid].steps == q.steps
+        assert np.array_equal(alone[0].state, res[q.rid].state), q.rid
+
+
+def test_batched_stages_match_oracle(srv, oracle):
+    """Three runs of different degrees, shell sizes and backgrounds advanced
+    together by sdm_batch_stage: each run's state after two SSPRK(5,3) steps
+    against the FP64 oracle's, within 1e-12 of max|u_v| + dt T_v.  The inputs
+    are made from the oracle's meshes."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2502_17805_amd import sdmhd as sd
+    runs = []
+    for (Nz, Nr, p, N_rho, seed) in ((2, 1, 5, 3.0, 1000), (2, 2, 5, 5.0, 1001), (2, 2, 3, 3.0, 1002)):
+        mo = oracle.Mesh.shell(p + 1, Nz, Nr)
+        bg = inp.Background(N_rho)
+        Q = inp.shell_state(mo.get("x_sp"), bg, seed)
+        pr = inp.run_params(seed, bg)
+        ch = inp.glm_speed(Q)
+        pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
+        s = sd.Solver(sd.shell(Nz, Nr, p))
         s.set_state(torch.from_numpy(Q))
         runs.append((s, sd.make_params(**pr), oracle.make_params(**pr), mo, Q))
     dt = 2e-3
-    import ctypes as C
     nb = C.c_size_t()
     sd._check(sd._lib.sdm_batch_workspace_size(len(runs), C.byref(nb)))
     bws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
