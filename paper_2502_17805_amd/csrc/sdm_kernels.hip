@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -144,24 +145,27 @@ struct Run {
   int32_t fuse;
   GBL double* out;
   double beta_dt;
-  Phys<T> P;
+  // the physical parameters stay in the descriptor (the kernels copy them
+  // to LDS with vector loads, so that they take no scalar registers); the
+  // two values needed before that copy is visible are kept here
+  const Phys<double>* P;
+  int32_t wall_kind[2];
+  bool kr_on;
 };
 
-template <typename T, typename S>
-__device__ __forceinline__ Phys<T> cvt_phys(S& p) {
-  Phys<T> o;
-  o.gm1 = (T)p.gm1; o.gamma = (T)p.gamma; o.Rgas = (T)p.Rgas; o.cp = (T)p.cp;
-  o.inv_R = (T)p.inv_R; o.inv_gamma = (T)p.inv_gamma;
-  o.GM = (T)p.GM; o.Omega = (T)p.Omega; o.nu = (T)p.nu; o.kappa = (T)p.kappa; o.eta = (T)p.eta;
-  o.kr_scale = (T)p.kr_scale; o.kr_c0 = (T)p.kr_c0; o.kr_c1 = (T)p.kr_c1; o.kr_c2 = (T)p.kr_c2;
-  o.kr_w = (T)p.kr_w; o.c_h = (T)p.c_h; o.glm_a = (T)p.glm_a;
-  o.q_wall[0] = (T)p.q_wall[0]; o.q_wall[1] = (T)p.q_wall[1];
-  o.T_wall[0] = (T)p.T_wall[0]; o.T_wall[1] = (T)p.T_wall[1];
-  o.powell = p.powell;
-  o.wall_kind[0] = p.wall_kind[0]; o.wall_kind[1] = p.wall_kind[1];
-  o.wall_mag[0] = p.wall_mag[0]; o.wall_mag[1] = p.wall_mag[1];
-  o.wall_th[0] = p.wall_th[0]; o.wall_th[1] = p.wall_th[1];
-  return o;
+// Phys<double> -> Phys<T> by lane: the 22 real parameters then the 7 int32
+// selectors (tid >= 29 copies nothing)
+template <typename T>
+__device__ __forceinline__ void copy_phys(const Phys<double>* src, Phys<T>* dst, int tid) {
+  constexpr int NR = 22, NS = 7;
+  static_assert(offsetof(Phys<T>, powell) == NR * sizeof(T) && offsetof(Phys<double>, powell) == NR * sizeof(double),
+                "real parameters first");
+  static_assert(sizeof(Phys<T>) >= NR * sizeof(T) + NS * sizeof(int32_t), "selectors after them");
+  if (tid < NR) {
+    reinterpret_cast<T*>(dst)[tid] = (T)reinterpret_cast<const double*>(src)[tid];
+  } else if (tid < NR + NS) {
+    reinterpret_cast<int32_t*>(&dst->powell)[tid - NR] = reinterpret_cast<const int32_t*>(&src->powell)[tid - NR];
+  }
 }
 
 template <typename T, typename S>
@@ -190,7 +194,10 @@ __device__ __forceinline__ void fill_run(Run<T>& r, S& d) {
   r.fuse = d.fuse;
   r.out = (GBL double*)d.out;
   r.beta_dt = d.beta_dt;
-  r.P = cvt_phys<T>(d.P);
+  r.P = (const Phys<double>*)&d.P;
+  r.wall_kind[0] = d.P.wall_kind[0];
+  r.wall_kind[1] = d.P.wall_kind[1];
+  r.kr_on = d.P.kr_scale != 0.0;
 }
 
 // the run and element of work item w (batched: the last run whose element
@@ -346,7 +353,7 @@ __device__ __forceinline__ void acc_vecs(T* acc, int base, T w, const typename R
 
 template <int N, typename T>
 __device__ __forceinline__ T interp_rows(const T* sR, const T* w, int ws, int s0, int st, T qf[9], T gf[27],
-                                         bool use_kr, const Run<T>& R) {
+                                         bool use_kr, const Run<T>& R, const Phys<T>& P) {
   constexpr int N3 = N * N * N;
   constexpr int RS = row_stride<T>();
   constexpr int W = RowVec<T>::W, NV = 36 / W, H0 = (NV + 1) / 2, H1 = NV - H0;
@@ -402,7 +409,7 @@ __device__ __forceinline__ T interp_rows(const T* sR, const T* w, int ws, int s0
       const int sidx = s0 + i * st;
       const T x[3] = {(T)R.x_sp[(R.e * 3 + 0) * N3 + sidx], (T)R.x_sp[(R.e * 3 + 1) * N3 + sidx],
                       (T)R.x_sp[(R.e * 3 + 2) * N3 + sidx]};
-      kf += w[i * ws] * kappa_r(x, R.P);
+      kf += w[i * ws] * kappa_r(x, P);
     }
   }
   return kf;
@@ -437,7 +444,7 @@ __device__ __forceinline__ void load_outside_state(const Run<T>& R, int ab, int3
     const int c2 = -code - 1, g = c2 & 3;
     const int64_t bf = c2 >> 2;
     if (g == 3) tn = R.imp_q + bf * 9 * N2 + ab;
-    else if (g == 2 || wsel(g, R.P.wall_kind) == 1) gh = R.ghost + bf * 9 * N2 + ab;
+    else if (g == 2 || wsel(g, R.wall_kind) == 1) gh = R.ghost + bf * 9 * N2 + ab;
   }
   if constexpr (sizeof(T) == 8) {
     if (gh) tn = (const GBL T*)gh;  // the ghost state is FP64 like the traces
@@ -687,12 +694,12 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
 
   {
     const int64_t e = R.e;
-    if (tid == 0) sP = R.P;
+    copy_phys<T>(R.P, &sP, tid);
     const Phys<T>& P = sP;  // valid after the barrier that ends phase A
     const GBL double* Qe = R.Q + e * 9 * N3;
     const GBL double* Se = R.S_fp + e * 9 * NF;
     const GBL int32_t* nb6 = R.nbr + e * 6;
-    const bool use_kr = R.P.kr_scale != T(0);
+    const bool use_kr = R.kr_on;
 
     // A. every global read of this element is issued before any of them is
     //    used (one round trip, plus one for the neighbour gather that needs
@@ -812,92 +819,47 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
     }
     __syncthreads();
 
-    // C. gradient at the solution points.
-    //    C1: derivative of each variable along each line: the solution
-    //    polynomial's own derivative plus the lifting of the two end jumps;
-    //    one (direction, line, variable) per item.  The N x (N + 2) table
-    //    entries (DI, and the end columns of D) are read from LDS into
-    //    registers once, where they fit; a thread then takes two items per
-    //    step, both items' LDS reads issued before either's arithmetic.
-    //    Written to the gradient slots of the point rows as dQ/dxi_d.
-    {
-      constexpr int NIT = 3 * 9 * N2;
-      constexpr bool CREG = N * (N + 2) * (int)sizeof(T) <= 384;
-      constexpr int K = CREG ? 2 : 1;
-      T cD[CREG ? N : 1][N + 2];
-      if constexpr (CREG) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-#pragma unroll
-          for (int j = 0; j < N; ++j) cD[i][j] = sDI[(i * N + j) * dis];
-          cD[i][N] = sD[(i * NP) * ds];
-          cD[i][N + 1] = sD[(i * NP + N) * ds];
-        }
-      }
-      for (int it0 = tid; it0 < NIT; it0 += K * BS) {
-        T ln[K][N], j0[K], jN[K];
-        int s0[K], st[K], v[K], d[K];
-        bool on[K];
-#pragma unroll
-        for (int u = 0; u < K; ++u) {
-          // an item past the end repeats item it0 (read only, not stored)
-          const int it = it0 + u * BS;
-          on[u] = it < NIT;
-          const int itc = on[u] ? it : it0;
-          v[u] = itc % 9;  // variable fastest
-          const int t = itc / 9, pq = t % N2;
-          d[u] = t / N2;
-          st[u] = d[u] == 0 ? 1 : (d[u] == 1 ? N : N2);
-          s0[u] = sp_line<N>(d[u], pq % N, pq / N, 0);
-#pragma unroll
-          for (int j = 0; j < N; ++j) ln[u][j] = sR[(s0[u] + j * st[u]) * RS + v[u]];
-          j0[u] = sU[((2 * d[u]) * N2 + pq) * 9 + v[u]];
-          jN[u] = sU[((2 * d[u] + 1) * N2 + pq) * 9 + v[u]];
-        }
-        if constexpr (CREG) {
-          T dd[K][N];
-#pragma unroll
-          for (int u = 0; u < K; ++u)
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-              T x = cD[i][N] * j0[u] + cD[i][N + 1] * jN[u];
-#pragma unroll
-              for (int j = 0; j < N; ++j) x += cD[i][j] * ln[u][j];
-              dd[u][i] = x;
-            }
-#pragma unroll
-          for (int u = 0; u < K; ++u)
-            if (on[u]) {
-              T* out = sR + 9 + v[u] * 3 + d[u];
-#pragma unroll
-              for (int i = 0; i < N; ++i) out[(s0[u] + i * st[u]) * RS] = dd[u][i];
-            }
-        } else {
-          T* out = sR + 9 + v[0] * 3 + d[0];
-#pragma unroll 1
-          for (int i = 0; i < N; ++i) {
-            T x = sD[(i * NP) * ds] * j0[0] + sD[(i * NP + N) * ds] * jN[0];
-#pragma unroll
-            for (int j = 0; j < N; ++j) x += sDI[(i * N + j) * dis] * ln[0][j];
-            out[(s0[0] + i * st[0]) * RS] = x;
-          }
-        }
-      }
-    }
-    __syncthreads();
-    //    C2: chain rule to physical space, grad_x Q = sum_d (S^d/|J|) dQ/dxi_d,
-    //    in place, one solution point per thread
+    // C. gradient at the solution points, one SP per thread: along each
+    //    direction d the derivative of the solution polynomial through the
+    //    line's N points plus the lifting of the line's two end jumps,
+    //    dQ/dxi_d = D_i0 J_0 + D_iN J_N + sum_j DI_ij Q_j, then the chain
+    //    rule grad_x Q = sum_d (S^d/|J|) dQ/dxi_d, summed in registers and
+    //    written to the gradient slots of the thread's own point row (the
+    //    Q slots other threads read are not written).  Each line row is
+    //    read as whole 16-byte units.
     if (tid < N3) {
+      T g[27];
 #pragma unroll
-      for (int v = 0; v < 9; ++v) {
-        T* g = sR + tid * RS + 9 + v * 3;
-        const T d0 = g[0], d1 = g[1], d2 = g[2];
+      for (int k = 0; k < 27; ++k) g[k] = T(0);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) g[c] = Sj[0][c] * d0 + Sj[1][c] * d1 + Sj[2][c] * d2;
+      for (int d = 0; d < 3; ++d) {
+        const int i = d == 0 ? ia0 : (d == 1 ? ia1 : ia2);
+        const int st = d == 0 ? 1 : (d == 1 ? N : N2);
+        const int pq = d == 0 ? ia1 + N * ia2 : (d == 1 ? ia0 + N * ia2 : ia0 + N * ia1);
+        const T* row0 = sR + (tid - i * st) * RS;
+        const T* j0 = sU + ((2 * d) * N2 + pq) * 9;
+        const T* jN = sU + ((2 * d + 1) * N2 + pq) * 9;
+        const T c0 = sD[(i * NP) * ds], cN = sD[(i * NP + N) * ds];
+        T dq[9];
+#pragma unroll
+        for (int v = 0; v < 9; ++v) dq[v] = c0 * j0[v] + cN * jN[v];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          const T w = sDI[(i * N + j) * dis];
+          const T* row = row0 + j * st * RS;
+#pragma unroll
+          for (int v = 0; v < 9; ++v) dq[v] += w * row[v];
+        }
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) g[v * 3 + c] += Sj[d][c] * dq[v];
       }
+      T* out = sR + tid * RS + 9;
+#pragma unroll
+      for (int k = 0; k < 27; ++k) out[k] = g[k];
     }
     __syncthreads();
-
     if (DIAG) {
       // per-element diagnostics: W^3 |J|-weighted sums, maxima, NaN flag
       double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -964,7 +926,7 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
       const int st = d == 0 ? 1 : (d == 1 ? N : N2);
       const int s0 = sp_line<N>(d, p, q, 0);
       T qf[9], gf[27];
-      T kf = interp_rows<N>(sR, sI + fe * N * is, is, s0, st, qf, gf, use_kr, R);
+      T kf = interp_rows<N>(sR, sI + fe * N * is, is, s0, st, qf, gf, use_kr, R, P);
       T qx[9], n[3];
       int32_t code;
       if (FACE_REG) {
@@ -1034,7 +996,7 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
         const int p = line % N, q = line / N;
         const int s0 = sp_line<N>(d, p, q, 0);
         T qf[9], gf[27];
-        T kf = interp_rows<N>(sR, sI + f * N * is, is, s0, st, qf, gf, use_kr, R);
+        T kf = interp_rows<N>(sR, sI + f * N * is, is, s0, st, qf, gf, use_kr, R, P);
         const T Sd[3] = {Sint[d][0], Sint[d][1], Sint[d][2]};
         ViscLocal<T> vl;
         viscous_local(qf, gf, kf, P, vl);
