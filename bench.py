@@ -70,10 +70,13 @@ def alg_bytes(kind, N, E, n_extra=1.2, fused=True):
 
 
 # FP64 operations (+, -, *, /, sqrt) of one call of each pointwise physics
-# function of the kernels, counted on the host from sdm_physics.hpp
-# (tests/flops/count_physics_flops.cpp; tests/test_flop_count.py keeps them
-# in step with the source)
-PHYS_FLOPS = {"flux_inviscid": 83, "viscous_local": 197, "flux_viscous7": 54, "rusanov": 329}
+# function of the FP64 oracle (oracle/sdmhd_oracle_point.inc), counted on
+# the host with an operation-counting number type
+# (tests/flops/count_oracle_flops.cpp; tests/test_flop_count.py keeps them in
+# step with the oracle source).  The kernels compute the same fluxes with
+# fewer operations; the algorithmic count is the method's, as the oracle
+# states it.
+PHYS_FLOPS = {"inv_flux": 92, "visc_flux": 266, "rusanov": 356}
 
 
 def alg_flops(N):
@@ -81,18 +84,18 @@ def alg_flops(N):
     Difference Method"): the tensor contractions as multiply-adds (Q to the
     flux points of each family, the derivative of the flux-point polynomial
     at the SPs, the 27 gradient components to the flux points, the flux
-    divergence, the chain rule), plus the pointwise physics counted from the
-    kernels' own formulas: per interior flux point the inviscid and viscous
-    fluxes through S^d (flux_inviscid + viscous_local + flux_viscous7 + 7),
-    per unique face point the Rusanov flux and both sides' viscous fluxes with
-    their average (rusanov + 2 (viscous_local + flux_viscous7) + 21), per SP
-    the sources and the scaling by 1/|J| (67).  Wall faces are counted as
-    interior faces; the RK update is not part of the residual."""
+    divergence, the chain rule), plus the pointwise physics as the oracle
+    computes it: per interior flux point the inviscid and viscous fluxes
+    through S^d and their difference (inv_flux + visc_flux + 9), per unique
+    face point the Rusanov flux, both sides' viscous fluxes and the BR1
+    average (rusanov + 2 visc_flux + 27), per SP the sources and the scaling
+    by 1/|J| (67).  Wall faces are counted as interior faces; the RK update
+    is not part of the residual."""
     N2, N3, NF = N * N, N ** 3, (N + 1) * N * N
     mac = 3 * 9 * NF * N + 3 * 9 * N3 * (N + 1) + 27 * 3 * NF * N + 3 * 9 * N3 * (N + 1) + 27 * 3 * N3
     f = PHYS_FLOPS
-    interior = f["flux_inviscid"] + f["viscous_local"] + f["flux_viscous7"] + 7
-    face = f["rusanov"] + 2 * (f["viscous_local"] + f["flux_viscous7"]) + 21
+    interior = f["inv_flux"] + f["visc_flux"] + 9
+    face = f["rusanov"] + 2 * f["visc_flux"] + 27
     point = interior * 3 * N2 * (N - 1) + face * 3 * N2 + 67 * N3
     return 2 * mac + point
 

@@ -115,8 +115,12 @@ def build_variant(source_text: str, path: str) -> str:
 
 
 def source_text() -> str:
+    """The oracle's C source with its pointwise-physics include inlined."""
     with open(_SRC) as f:
-        return f.read()
+        src = f.read()
+    inc = '#include "sdmhd_oracle_point.inc"'
+    with open(os.path.join(_HERE, "sdmhd_oracle_point.inc")) as f:
+        return src.replace(inc, f.read())
 
 
 def swap_library(path):

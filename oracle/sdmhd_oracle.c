@@ -629,123 +629,7 @@ int or_mesh_get(const or_mesh* m, const char* name, void* out) {
 /* Pointwise physics (Sec. MHD Governing Equations)                    */
 /* ------------------------------------------------------------------ */
 
-/* pressure from the total energy including the GLM term (Eq. energy) */
-static double pressure(const double* q, const or_params* P) {
-  double rho = q[0];
-  double ke = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / rho;
-  double pm = 0.5 * (q[5] * q[5] + q[6] * q[6] + q[7] * q[7]);
-  return (P->gamma - 1.0) * (q[4] - ke - pm - 0.5 * q[8] * q[8]);
-}
-
-/* Inviscid GLM-MHD flux dotted with an (unnormalised) direction n
- * (Eq. invF; the energy row's GLM term is read as c_h psi B, the induction
- * row's as c_h psi I; e = E - psi^2/2). */
-static void inv_flux(const double* q, const double* n, const or_params* P, double* F) {
-  double rho = q[0], u[3] = {q[1] / rho, q[2] / rho, q[3] / rho};
-  const double* B = &q[5];
-  double psi = q[8];
-  double p = pressure(q, P);
-  double pm = 0.5 * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
-  double un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
-  double Bn = B[0] * n[0] + B[1] * n[1] + B[2] * n[2];
-  double uB = u[0] * B[0] + u[1] * B[1] + u[2] * B[2];
-  double e = q[4] - 0.5 * psi * psi;
-  F[0] = rho * un;
-  for (int i = 0; i < 3; ++i) F[1 + i] = q[1 + i] * un + (p + pm) * n[i] - B[i] * Bn;
-  F[4] = un * (e + p + pm) - Bn * uB + P->c_h * psi * Bn;
-  for (int i = 0; i < 3; ++i) F[5 + i] = un * B[i] - Bn * u[i] + P->c_h * psi * n[i];
-  F[8] = P->c_h * Bn;
-}
-
-typedef struct {
-  double u[3], B[3], tau[3][3], q[3], J[3];
-} visc_t;
-
-/* Viscous quantities from a state q and its physical gradient G[v*3+j]:
- * shear stress (Eq. ssTensor, Stokes lambda = -2/3 mu, mu = rho*nu), heat
- * flux (Eq. qFlux, with grad S from Eq. entropy by the chain rule), current
- * J = curl B.  kr = radiative diffusivity at the point. */
-static void visc_state(const double* q, const double* G, double kr, const or_params* P, visc_t* v) {
-  const double g = P->gamma, R = P->Rgas, cp = g * R / (g - 1.0);
-  double rho = q[0];
-  for (int i = 0; i < 3; ++i) { v->u[i] = q[1 + i] / rho; v->B[i] = q[5 + i]; }
-  double psi = q[8];
-  double p = pressure(q, P);
-  double T = p / (rho * R);
-  double uu = v->u[0] * v->u[0] + v->u[1] * v->u[1] + v->u[2] * v->u[2];
-  double du[3][3], dp[3], dT[3], dS[3];
-  for (int j = 0; j < 3; ++j) {
-    for (int i = 0; i < 3; ++i) du[i][j] = (G[(1 + i) * 3 + j] - v->u[i] * G[0 * 3 + j]) / rho;
-    double um = 0.0, bb = 0.0;
-    for (int i = 0; i < 3; ++i) { um += v->u[i] * G[(1 + i) * 3 + j]; bb += v->B[i] * G[(5 + i) * 3 + j]; }
-    dp[j] = (g - 1.0) * (G[4 * 3 + j] - um + 0.5 * uu * G[0 * 3 + j] - bb - psi * G[8 * 3 + j]);
-    dT[j] = (dp[j] - R * T * G[0 * 3 + j]) / (rho * R);
-    dS[j] = cp * (dp[j] / (g * p) - G[0 * 3 + j] / rho);
-  }
-  double mu = rho * P->nu;
-  double divu = du[0][0] + du[1][1] + du[2][2];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      v->tau[i][j] = mu * (du[i][j] + du[j][i]) + (i == j ? -2.0 / 3.0 * mu * divu : 0.0);
-  for (int j = 0; j < 3; ++j) v->q[j] = -P->kappa * rho * T * dS[j] - kr * rho * cp * dT[j];
-  /* J_x = dBz/dy - dBy/dz, ... */
-  v->J[0] = G[7 * 3 + 1] - G[6 * 3 + 2];
-  v->J[1] = G[5 * 3 + 2] - G[7 * 3 + 0];
-  v->J[2] = G[6 * 3 + 0] - G[5 * 3 + 1];
-}
-
-/* Viscous flux dotted with n (Eq. visF; the induction row eta*curl(B) is
- * read as the antisymmetric tensor eta (dB_i/dx_j - dB_j/dx_i), whose flux
- * through n is eta J x n). */
-static void visc_flux(const double* q, const double* G, double kr, const double* n,
-                      const or_params* P, double* F) {
-  visc_t v;
-  visc_state(q, G, kr, P, &v);
-  double tn[3];
-  for (int i = 0; i < 3; ++i) tn[i] = v.tau[i][0] * n[0] + v.tau[i][1] * n[1] + v.tau[i][2] * n[2];
-  double BxJ[3] = {v.B[1] * v.J[2] - v.B[2] * v.J[1], v.B[2] * v.J[0] - v.B[0] * v.J[2],
-                   v.B[0] * v.J[1] - v.B[1] * v.J[0]};
-  F[0] = 0.0;
-  for (int i = 0; i < 3; ++i) F[1 + i] = tn[i];
-  F[4] = (v.u[0] * tn[0] + v.u[1] * tn[1] + v.u[2] * tn[2]) -
-         (v.q[0] * n[0] + v.q[1] * n[1] + v.q[2] * n[2]) +
-         P->eta * (BxJ[0] * n[0] + BxJ[1] * n[1] + BxJ[2] * n[2]);
-  F[5] = P->eta * (v.J[1] * n[2] - v.J[2] * n[1]);
-  F[6] = P->eta * (v.J[2] * n[0] - v.J[0] * n[2]);
-  F[7] = P->eta * (v.J[0] * n[1] - v.J[1] * n[0]);
-  F[8] = 0.0;
-}
-
-/* fast magnetosonic speed along the unit direction nh */
-static double fast_speed(const double* q, const double* nh, const or_params* P) {
-  double rho = q[0], p = pressure(q, P);
-  double a2 = P->gamma * p / rho;
-  double b2 = (q[5] * q[5] + q[6] * q[6] + q[7] * q[7]) / rho;
-  double Bn = q[5] * nh[0] + q[6] * nh[1] + q[7] * nh[2];
-  double bn2 = Bn * Bn / rho;
-  double s = a2 + b2;
-  double disc = s * s - 4.0 * a2 * bn2;
-  if (disc < 0.0) disc = 0.0;
-  return sqrt(0.5 * (s + sqrt(disc)));
-}
-
-/* Rusanov common inviscid flux through the unnormalised normal n from the
- * left state qL to the right state qR; the dissipation speed includes the
- * GLM speed c_h. */
-static void rusanov(const double* qL, const double* qR, const double* n, const or_params* P, double* F) {
-  double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-  double nh[3] = {n[0] / nn, n[1] / nn, n[2] / nn};
-  double unL = (qL[1] * nh[0] + qL[2] * nh[1] + qL[3] * nh[2]) / qL[0];
-  double unR = (qR[1] * nh[0] + qR[2] * nh[1] + qR[3] * nh[2]) / qR[0];
-  double lam = fabs(unL) + fast_speed(qL, nh, P);
-  double lr = fabs(unR) + fast_speed(qR, nh, P);
-  if (lr > lam) lam = lr;
-  if (P->c_h > lam) lam = P->c_h;
-  double FL[NV], FR[NV];
-  inv_flux(qL, n, P, FL);
-  inv_flux(qR, n, P, FR);
-  for (int v = 0; v < NV; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * nn * (qR[v] - qL[v]);
-}
+#include "sdmhd_oracle_point.inc"
 
 /* ------------------------------------------------------------------ */
 /* Wall and Dirichlet faces (Sec. Problem Formulation and Boundary       */

@@ -153,11 +153,11 @@ struct Run {
   bool kr_on;
 };
 
-// Phys<double> -> Phys<T> by lane: the 22 real parameters then the 7 int32
+// Phys<double> -> Phys<T> by lane: the 23 real parameters then the 7 int32
 // selectors (tid >= 29 copies nothing)
 template <typename T>
 __device__ __forceinline__ void copy_phys(const Phys<double>* src, Phys<T>* dst, int tid) {
-  constexpr int NR = 22, NS = 7;
+  constexpr int NR = 23, NS = 7;
   static_assert(offsetof(Phys<T>, powell) == NR * sizeof(T) && offsetof(Phys<double>, powell) == NR * sizeof(double),
                 "real parameters first");
   static_assert(sizeof(Phys<T>) >= NR * sizeof(T) + NS * sizeof(int32_t), "selectors after them");
@@ -944,9 +944,10 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
       if (code >= 0 || g == 3) {
         // interior (or import) face: Rusanov on the symmetric normal, own half
         // of the BR1 viscous flux
-        viscous_local(qf, gf, kf, P, vl);
+        PointState<T> ps;
+        point_state(qf, P, ps);
         T Fv[7];
-        flux_viscous7(vl, n, P, Fv);
+        flux_viscous_n(qf, gf, kf, ps, n, P, Fv);
         GBL T* vt = R.Vtr + (e * 6 + face) * 7 * N2 + ab;
 #pragma unroll
         for (int c = 0; c < 7; ++c) vt[c * N2] = Fv[c];
@@ -958,12 +959,13 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
         // fluxes of both states with the interior gradient
         rusanov(qf, qx, n, P, F);
         T Fv[7];
-        viscous_local(qf, gf, kf, P, vl);
-        flux_viscous7(vl, n, P, Fv);
+        PointState<T> ps;
+        point_state(qf, P, ps);
+        flux_viscous_n(qf, gf, kf, ps, n, P, Fv);
 #pragma unroll
         for (int c = 0; c < 7; ++c) F[1 + c] -= T(0.5) * Fv[c];
-        viscous_local(qx, gf, kf, P, vl);
-        flux_viscous7(vl, n, P, Fv);
+        point_state(qx, P, ps);
+        flux_viscous_n(qx, gf, kf, ps, n, P, Fv);
 #pragma unroll
         for (int c = 0; c < 7; ++c) F[1 + c] -= T(0.5) * Fv[c];
       } else {
@@ -998,11 +1000,11 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
         T qf[9], gf[27];
         T kf = interp_rows<N>(sR, sI + f * N * is, is, s0, st, qf, gf, use_kr, R, P);
         const T Sd[3] = {Sint[d][0], Sint[d][1], Sint[d][2]};
-        ViscLocal<T> vl;
-        viscous_local(qf, gf, kf, P, vl);
+        PointState<T> ps;
+        point_state(qf, P, ps);
         T Fv[7];
-        flux_viscous7(vl, Sd, P, Fv);
-        flux_inviscid(qf, Sd, P, F);
+        flux_viscous_n(qf, gf, kf, ps, Sd, P, Fv);
+        flux_inviscid_s(qf, ps, Sd, P, F);
 #pragma unroll
         for (int c = 0; c < 7; ++c) F[1 + c] -= Fv[c];
       }
@@ -1384,6 +1386,7 @@ Phys<double> to_phys(const sdm_params* p) {
   o.cp = p->gamma * p->Rgas / (p->gamma - 1.0);
   o.inv_R = 1.0 / p->Rgas;
   o.inv_gamma = 1.0 / p->gamma;
+  o.inv_gm1 = 1.0 / (p->gamma - 1.0);
   o.GM = p->GM; o.Omega = p->Omega; o.nu = p->nu; o.kappa = p->kappa; o.eta = p->eta;
   o.kr_scale = p->kr_scale; o.kr_c0 = p->kr_c0; o.kr_c1 = p->kr_c1; o.kr_c2 = p->kr_c2;
   o.kr_w = p->kr_omega_per_r;

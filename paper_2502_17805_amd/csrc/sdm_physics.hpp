@@ -16,7 +16,7 @@ struct Phys {
   T gamma;
   T Rgas;
   T cp;        // gamma R / (gamma - 1)
-  T inv_R, inv_gamma;
+  T inv_R, inv_gamma, inv_gm1;
   T GM, Omega, nu, kappa, eta;
   T kr_scale, kr_c0, kr_c1, kr_c2, kr_w;
   T c_h, glm_a;
@@ -148,6 +148,92 @@ __device__ __forceinline__ void flux_viscous7(const ViscLocal<T>& v, const T n[3
   Fv[4] = P.eta * (v.J[1] * n[2] - v.J[2] * n[1]);
   Fv[5] = P.eta * (v.J[2] * n[0] - v.J[0] * n[2]);
   Fv[6] = P.eta * (v.J[0] * n[1] - v.J[1] * n[0]);
+}
+
+// ---- fused fluxes of the interior and face flux points --------------------
+// The inviscid and viscous fluxes of one state share 1/rho, u, p and T, and
+// only their component along n is needed, so the gradients are projected on
+// n before they are combined.  The heat flux through n uses Eq. "qFlux" with
+// grad S from Eq. "entropy" and the ideal gas p = rho R T, c_p/(gamma R) =
+// 1/(gamma - 1):  -kappa rho T grad S - kappa_r rho c_p grad T
+//   = -(kappa + gamma kappa_r)/(gamma - 1) grad p + (kappa + kappa_r) c_p T grad rho.
+
+template <typename T>
+struct PointState {
+  T ir, u[3], uu, pm, p, Tt;
+};
+
+template <typename T>
+__device__ __forceinline__ void point_state(const T* q, const Phys<T>& P, PointState<T>& s) {
+  s.ir = recip(q[0]);
+  s.u[0] = q[1] * s.ir; s.u[1] = q[2] * s.ir; s.u[2] = q[3] * s.ir;
+  s.uu = s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2];
+  s.pm = T(0.5) * (q[5] * q[5] + q[6] * q[6] + q[7] * q[7]);
+  s.p = P.gm1 * (q[4] - T(0.5) * (q[1] * s.u[0] + q[2] * s.u[1] + q[3] * s.u[2]) - s.pm - T(0.5) * q[8] * q[8]);
+  s.Tt = s.p * s.ir * P.inv_R;
+}
+
+// flux_inviscid from a point state (same formulas)
+template <typename T>
+__device__ __forceinline__ void flux_inviscid_s(const T* q, const PointState<T>& s, const T n[3], const Phys<T>& P,
+                                                T F[9]) {
+  const T un = s.u[0] * n[0] + s.u[1] * n[1] + s.u[2] * n[2];
+  const T Bn = q[5] * n[0] + q[6] * n[1] + q[7] * n[2];
+  const T uB = s.u[0] * q[5] + s.u[1] * q[6] + s.u[2] * q[7];
+  const T pt = s.p + s.pm;
+  const T e = q[4] - T(0.5) * q[8] * q[8];
+  F[0] = q[0] * un;
+  F[1] = q[1] * un + pt * n[0] - q[5] * Bn;
+  F[2] = q[2] * un + pt * n[1] - q[6] * Bn;
+  F[3] = q[3] * un + pt * n[2] - q[7] * Bn;
+  F[4] = un * (e + pt) - Bn * uB + P.c_h * q[8] * Bn;
+  F[5] = un * q[5] - Bn * s.u[0] + P.c_h * q[8] * n[0];
+  F[6] = un * q[6] - Bn * s.u[1] + P.c_h * q[8] * n[1];
+  F[7] = un * q[7] - Bn * s.u[2] + P.c_h * q[8] * n[2];
+  F[8] = P.c_h * Bn;
+}
+
+// Components 1..7 of the viscous flux through n (Eq. "visF"; the same
+// quantities as viscous_local + flux_viscous7): Fv[0..2] = tau n, Fv[3] =
+// u.(tau n) - q.n + eta (B x J).n, Fv[4..6] = eta J x n.
+template <typename T>
+__device__ __forceinline__ void flux_viscous_n(const T* q, const T* G, T kr, const PointState<T>& s, const T n[3],
+                                               const Phys<T>& P, T Fv[7]) {
+  const T grn = G[0] * n[0] + G[1] * n[1] + G[2] * n[2];
+  T gmn[3], gBn[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    gmn[i] = G[(1 + i) * 3] * n[0] + G[(1 + i) * 3 + 1] * n[1] + G[(1 + i) * 3 + 2] * n[2];
+    gBn[i] = G[(5 + i) * 3] * n[0] + G[(5 + i) * 3 + 1] * n[1] + G[(5 + i) * 3 + 2] * n[2];
+  }
+  const T gEn = G[12] * n[0] + G[13] * n[1] + G[14] * n[2];
+  const T gpn = G[24] * n[0] + G[25] * n[1] + G[26] * n[2];
+  // velocity gradient du_ij = (d m_i/dx_j - u_i d rho/dx_j) / rho
+  T du[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) du[i][j] = (G[(1 + i) * 3 + j] - s.u[i] * G[j]) * s.ir;
+  const T mu = q[0] * P.nu;
+  const T lam = T(-2.0 / 3.0) * mu * (du[0][0] + du[1][1] + du[2][2]);
+  T tn[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    tn[i] = mu * ((du[i][0] + du[0][i]) * n[0] + (du[i][1] + du[1][i]) * n[1] + (du[i][2] + du[2][i]) * n[2]) +
+            lam * n[i];
+  // grad p . n (from the conserved gradients) and the heat flux through n
+  const T dpn = P.gm1 * (gEn - (s.u[0] * gmn[0] + s.u[1] * gmn[1] + s.u[2] * gmn[2]) + T(0.5) * s.uu * grn -
+                         (q[5] * gBn[0] + q[6] * gBn[1] + q[7] * gBn[2]) - q[8] * gpn);
+  const T qn = -(P.kappa + P.gamma * kr) * P.inv_gm1 * dpn + (P.kappa + kr) * P.cp * s.Tt * grn;
+  const T J0 = G[21 + 1] - G[18 + 2], J1 = G[15 + 2] - G[21 + 0], J2 = G[18 + 0] - G[15 + 1];
+  const T bxjn = (q[6] * J2 - q[7] * J1) * n[0] + (q[7] * J0 - q[5] * J2) * n[1] + (q[5] * J1 - q[6] * J0) * n[2];
+  Fv[0] = tn[0];
+  Fv[1] = tn[1];
+  Fv[2] = tn[2];
+  Fv[3] = (s.u[0] * tn[0] + s.u[1] * tn[1] + s.u[2] * tn[2]) - qn + P.eta * bxjn;
+  Fv[4] = P.eta * (J1 * n[2] - J2 * n[1]);
+  Fv[5] = P.eta * (J2 * n[0] - J0 * n[2]);
+  Fv[6] = P.eta * (J0 * n[1] - J1 * n[0]);
 }
 
 // fast magnetosonic speed along the unit direction nh
