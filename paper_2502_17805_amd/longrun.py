@@ -2,10 +2,12 @@
 
   python -m paper_2502_17805_amd.longrun --mesh 12,8 --p 5 --n-rho 3 --seed 1 \
       --steps 1000 --every 50 [--arith 0,1] [--cfl 0.1] [--profiles 8,16] [--setup solar]
+      [--ch-every 100]
 
 Prints one JSON line: for each arithmetic the diagnostics every `every` steps
 (mass, total energy, volume-averaged kinetic and magnetic energy, max and L2
-|div B|, max |psi|, NaN flag) and, when both arithmetics ran, the relative
+|div B|, max |psi|, NaN flag, the largest signal speed max(|u| + c_f) of the
+state) and, when both arithmetics ran, the relative
 difference of KE, E_B and max|div B| of the FP32-mixed run from the FP64 run
 at each checkpoint.  With --profiles n_r,n_th it also reports, per
 arithmetic, the poloidal and toroidal magnetic energies at each checkpoint
@@ -31,12 +33,18 @@ from . import sdmhd as sd
 DIAG_NAMES = ("volume", "mass", "energy", "KE", "E_B", "max_divB", "L2_divB", "max_psi", "nan")
 
 
-def run(mesh, Q, pr, dt, steps, every, arith, label="", bins=None):
+def run(mesh, Q, pr, dt, steps, every, arith, label="", bins=None, ch_every=0, depth=0.28, cfl=0.1):
+    """ch_every > 0: every that many steps the GLM speed c_h is reset to the
+    current maximum signal speed max(|u| + c_f) over the SPs, the damping to
+    c_h / depth and dt to the CFL step of the current state (otherwise all
+    three stay at their t = 0 values).  Returns the diagnostic rows (with
+    c_h and dt appended when ch_every > 0) and the spherical profiles."""
     import torch
     s = sd.Solver(mesh, arith=arith)
+    pr = dict(pr)
     prm = sd.make_params(**pr)
     s.set_state(torch.from_numpy(Q))
-    rows = [[0, 0.0] + list(s.diagnostics(prm)[:9])]
+    rows = [[0, 0.0] + list(s.diagnostics(prm)[:9]) + [inp.glm_speed(Q)] + ([pr["c_h"], dt] if ch_every else [])]
     sph = {"E_Bpol": [], "E_Btor": []}
     acc = None
 
@@ -52,11 +60,22 @@ def run(mesh, Q, pr, dt, steps, every, arith, label="", bins=None):
     if bins is not None:
         sample(0)
     t0 = time.perf_counter()
+    t = 0.0
     for k in range(1, steps + 1):
         s.step(prm, dt)
+        t += dt
+        if ch_every and k % ch_every == 0:
+            q = s.state.cpu().numpy()
+            if np.isfinite(q).all():
+                ch = inp.glm_speed(q)
+                pr.update(c_h=ch, glm_a=ch / depth)
+                prm = sd.make_params(**pr)
+                dt = inp.time_step(q, mesh.Sj_sp, ch, cfl)
         if k % every == 0 or k == steps:
             d = s.diagnostics(prm)
-            rows.append([k, k * dt] + list(d[:9]))
+            q = s.state.cpu().numpy()
+            sig = inp.glm_speed(q) if np.isfinite(q).all() else float("nan")
+            rows.append([k, t] + list(d[:9]) + [sig] + ([pr["c_h"], dt] if ch_every else []))
             if bins is not None:
                 sample(k)
             print(f"# {label} arith={arith} step {k}: KE={d[3]:.6e} E_B={d[4]:.6e} max|divB|={d[5]:.3e} "
@@ -84,6 +103,10 @@ def main(argv=None):
     ap.add_argument("--cfl", type=float, default=0.1)
     ap.add_argument("--profiles", default="", metavar="N_R,N_TH",
                     help="also report spherical-component diagnostics on n_r x n_th (r, theta) bins")
+    ap.add_argument("--damping", type=float, default=1.0,
+                    help="GLM damping a = damping * c_h / (r_t - r_b) (default 1)")
+    ap.add_argument("--ch-every", type=int, default=0,
+                    help="reset c_h (and the GLM damping and dt) to the current state every that many steps")
     ap.add_argument("--setup", default="seeded", choices=("seeded", "solar"),
                     help="seeded: the polytrope with seeded transport coefficients and heat input; solar: "
                          "the solar benchmark's parameters on its flux-balanced background")
@@ -106,11 +129,16 @@ def main(argv=None):
         Q = inp.shell_state(mesh.x_sp, bg, a.seed)
         pr = inp.run_params(a.seed, bg)
     ch = inp.glm_speed(Q)
-    pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
+    depth = (bg.rt - bg.rb) / a.damping
+    pr.update(c_h=ch, glm_a=ch / depth)
     dt = inp.time_step(Q, mesh.Sj_sp, ch, a.cfl)
     label = f"{a.setup} shell 6x{Nz}x{Nz}x{Nr} p={a.p} N_rho={a.n_rho:g}"
-    out = {"workload": f"{label}, seed {a.seed}, {a.steps} SSPRK(5,3) steps, CFL {a.cfl:g}",
-           "elements": mesh.E, "dt": dt, "columns": ["step", "t", *DIAG_NAMES], "runs": {}}
+    out = {"workload": f"{label}, seed {a.seed}, {a.steps} SSPRK(5,3) steps, CFL {a.cfl:g}"
+                       + (f", GLM damping x{a.damping:g}" if a.damping != 1.0 else "")
+                       + (f", c_h, damping and dt reset every {a.ch_every} steps" if a.ch_every else ""),
+           "elements": mesh.E, "dt": dt,
+           "columns": ["step", "t", *DIAG_NAMES, "max_signal"] + (["c_h", "dt"] if a.ch_every else []),
+           "runs": {}}
     bins = None
     if a.profiles:
         n_r, n_th = (int(x) for x in a.profiles.split(","))
@@ -118,7 +146,7 @@ def main(argv=None):
         out["profile_bins"] = {"n_r": n_r, "n_th": n_th, "r": [bg.rb, bg.rt], "theta": [0.0, float(np.pi)]}
     for ar in (int(x) for x in a.arith.split(",")):
         key = "fp64" if ar == 0 else "fp32-mixed"
-        out["runs"][key], sph = run(mesh, Q, pr, dt, a.steps, a.every, ar, label, bins)
+        out["runs"][key], sph = run(mesh, Q, pr, dt, a.steps, a.every, ar, label, bins, a.ch_every, depth, a.cfl)
         if sph is not None:
             out.setdefault("spherical", {})[key] = sph
     r = out["runs"]
