@@ -53,5 +53,9 @@ def build_c_driver(lib=LIB) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--define", action="append", default=[], metavar="NAME=VALUE",
+                    help="extra preprocessor definition for the kernels (e.g. SDM_MFMA_INTERP=1)")
+    build(defines=ap.parse_args().define)
     sys.exit(0)

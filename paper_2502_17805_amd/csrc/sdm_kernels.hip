@@ -645,6 +645,38 @@ constexpr int volume_waves() {
   return sizeof(T) == 8 ? SDM_VOLUME_WAVES_F64 : SDM_VOLUME_WAVES_F32;
 }
 
+// Interior flux points of one family on FP64 MFMA (v_mfma_f64_4x4x4f64, four
+// 4x4 blocks per instruction; lane L supplies A[(L/4)%4][L%4][L/16] and
+// B[(L/4)%4][L/16][L%4] and receives D[(L/4)%4][L/16][L%4]).  With the
+// interpolation weights I[1 + m][i] as A and the point-row values of 16 lines
+// as B, lane o of wave w < 2 receives flux point f = 1 + o/16 of line
+// 16 w + o%16, all 36 fields in its accumulators (128 points); wave 2 takes
+// the other 52 (f = 1..4 of lines 32..35, f = 5 of every line) on the VALU.
+// Degree 5, FP64 only.  Measured no faster than the VALU interpolation
+// (same time within 2 %), so it is off unless built with SDM_MFMA_INTERP=1.
+#ifndef SDM_MFMA_INTERP
+#define SDM_MFMA_INTERP 0
+#endif
+template <int N, typename T>
+constexpr bool mfma_interior() {
+  return SDM_MFMA_INTERP && N == 6 && sizeof(T) == 8;
+}
+// the interior flux point (line, f) of thread tid in that arrangement
+__device__ __forceinline__ bool int_fp_mfma6(int tid, int& line, int& f) {
+  const int w = tid >> 6, o = tid & 63;
+  if (w < 2) {
+    f = 1 + (o >> 4);
+    line = 16 * w + (o & 15);
+    return true;
+  }
+  if (w == 2 && o < 52) {
+    f = o < 16 ? 1 + (o >> 2) : 5;
+    line = o < 16 ? 32 + (o & 3) : o - 16;
+    return true;
+  }
+  return false;
+}
+
 template <int N, typename T>
 struct VolLds {
   static constexpr int N2 = N * N, N3 = N2 * N, NI = N2 * (N - 1), BS = block_threads<N>();
@@ -734,9 +766,12 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
     }
     T fq[9], fn[3];  // face point: outside state (neighbour trace or ghost), normal
     if (has_face) load_normal<N>(R, lf, lab, fn);
-    T Sint[3][3];  // metric at the interior flux point `tid` of each family
-    if (!DIAG && INT_REG && tid < NI) {
-      const int line = tid / (N - 1), f = 1 + tid % (N - 1);
+    T Sint[3][3];  // metric at this thread's interior flux point of each family
+    int int_line = tid / (N - 1), int_f = 1 + tid % (N - 1);
+    bool int_on = INT_REG && tid < NI;
+    if constexpr (mfma_interior<N, T>()) int_on = int_fp_mfma6(tid, int_line, int_f);
+    if (!DIAG && int_on) {
+      const int line = int_line, f = int_f;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const int fi = fp_fam<N>(d, f, line % N, line / N);
@@ -992,13 +1027,42 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       T F[9];
-      if (tid < NI) {
-        const int st = d == 0 ? 1 : (d == 1 ? N : N2);
-        const int line = tid / (N - 1), f = 1 + tid % (N - 1);
-        const int p = line % N, q = line / N;
-        const int s0 = sp_line<N>(d, p, q, 0);
-        T qf[9], gf[27];
-        T kf = interp_rows<N>(sR, sI + f * N * is, is, s0, st, qf, gf, use_kr, R, P);
+      T qf[9], gf[27], kf = T(0);
+      const int st = d == 0 ? 1 : (d == 1 ? N : N2);
+      if (mfma_interior<N, T>() && __builtin_amdgcn_readfirstlane(tid >> 6) < 2) {
+        // waves 0, 1: 72 MFMAs (36 fields x two K chunks of 4 SPs, the
+        // chunk past the line's 6 SPs weighted 0), every lane active
+        const int w = __builtin_amdgcn_readfirstlane(tid >> 6), o = tid & 63;
+        const int m = o & 3, k = o >> 4;
+        const T a0 = sI[((1 + m) * N + k) * is];
+        const T a1 = (4 + k < N) ? sI[((1 + m) * N + 4 + k) * is] : T(0);
+        const int lineB = 16 * w + (o & 15);
+        const int s0B = sp_line<N>(d, lineB % N, lineB / N, 0);
+        const T* rb0 = sR + (s0B + k * st) * RS;
+        const bool ok1 = 4 + k < N;
+        const T* rb1 = sR + (s0B + (ok1 ? 4 + k : 0) * st) * RS;
+#pragma unroll
+        for (int v = 0; v < 36; ++v) {
+          const T b1 = ok1 ? rb1[v] : T(0);
+          T x = __builtin_amdgcn_mfma_f64_4x4x4f64(a0, rb0[v], T(0), 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f64_4x4x4f64(a1, b1, x, 0, 0, 0);
+          if (v < 9) qf[v] = x; else gf[v - 9] = x;
+        }
+        if (use_kr) {
+          const int s0 = sp_line<N>(d, int_line % N, int_line / N, 0);
+#pragma unroll 1
+          for (int i = 0; i < N; ++i) {
+            const int sidx = s0 + i * st;
+            const T x[3] = {(T)R.x_sp[(R.e * 3 + 0) * N3 + sidx], (T)R.x_sp[(R.e * 3 + 1) * N3 + sidx],
+                            (T)R.x_sp[(R.e * 3 + 2) * N3 + sidx]};
+            kf += sI[(int_f * N + i) * is] * kappa_r(x, P);
+          }
+        }
+      } else if (int_on) {
+        const int s0 = sp_line<N>(d, int_line % N, int_line / N, 0);
+        kf = interp_rows<N>(sR, sI + int_f * N * is, is, s0, st, qf, gf, use_kr, R, P);
+      }
+      if (int_on) {
         const T Sd[3] = {Sint[d][0], Sint[d][1], Sint[d][2]};
         PointState<T> ps;
         point_state(qf, P, ps);
@@ -1024,9 +1088,10 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
         }
       }
       __syncthreads();
-      if (tid < NI) {
+      if (int_on) {
+        const int slot = int_line * (N - 1) + int_f - 1;
 #pragma unroll
-        for (int v = 0; v < 9; ++v) sU[tid * 9 + v] = F[v];
+        for (int v = 0; v < 9; ++v) sU[slot * 9 + v] = F[v];
       }
       __syncthreads();
     }
