@@ -130,7 +130,8 @@ sdm_status sdm_tables(int p, double* xs, double* xf, double* I, double* D, doubl
  * points and N + 1 Legendre-Gauss flux points with both end points per
  * direction, the Lagrange bases h_i on the former and l_i on the latter).
  * arith: 0 = FP64 throughout; 1 = mixed (FP32 residual arithmetic, FP64
- * state, RK accumulation, metrics and diagnostics).  p in 1..6 (the FP64
+ * state, RK accumulation and diagnostics; the residual reads an FP32 copy of
+ * the geometry, see sdm_mesh_bind).  p in 1..6 (the FP64
  * volume kernel of p = 7 would exceed the 160 KB of LDS).  Uploads the 1-D
  * tables to the device's constant memory once per device; *out is owned by
  * the caller and released with sdm_destroy.  SDM_EUNSUPPORTED for p outside
@@ -144,7 +145,13 @@ sdm_status sdm_destroy(sdm_ctx* ctx);
  * equations are solved in the transformed form of Eq. "G.E. comp"); they
  * must outlive every call that uses them.  sdm_mesh_bind copies the
  * neighbour table to the host once to check every code decodes into range
- * (SDM_EINVAL otherwise) and stores the pointers. */
+ * (SDM_EINVAL otherwise) and stores the pointers.  With arith 1 it also
+ * allocates, on the context's device, FP32 copies (rounded to nearest) of
+ * x_sp, detJ, S_fp, Sj_sp and n_face, 22.9 KB per element at p = 5, which the
+ * FP32 residual kernels read instead (the values they would round on use, at
+ * half the bytes); the context owns them until sdm_destroy or the next bind,
+ * so rebind after changing those arrays.  Synchronous; SDM_EHIP if the
+ * allocation fails. */
 typedef struct {
   int64_t n_elem;
   int64_t n_bfaces;

@@ -83,6 +83,13 @@ struct RunDesc {
   const double* Sj_sp;
   const int32_t* nbr;
   const double* n_face;
+  // FP32 copies of the five geometry arrays (mixed arithmetic; made by
+  // sdm_mesh_bind), read by the FP32 kernels in place of the FP64 ones
+  const float* x_sp_f;
+  const float* detJ_f;
+  const float* S_fp_f;
+  const float* Sj_sp_f;
+  const float* n_face_f;
   const double* ghost;
   const void* imp_q;   // [n_bfaces][9][N2]  T  neighbour traces on import faces
   const void* imp_v;   // [n_bfaces][7][N2]  T  neighbour viscous normal fluxes
@@ -124,12 +131,15 @@ struct Launch {
 template <typename T>
 struct Run {
   int64_t e;  // element index within the run
-  const GBL double* x_sp;
-  const GBL double* detJ;
-  const GBL double* S_fp;
-  const GBL double* Sj_sp;
+  // geometry in the residual arithmetic (FP32-mixed reads FP32 copies); the
+  // diagnostics' quadrature takes |J| in FP64 in either arithmetic
+  const GBL T* x_sp;
+  const GBL T* detJ;
+  const GBL T* S_fp;
+  const GBL T* Sj_sp;
   const GBL int32_t* nbr;
-  const GBL double* n_face;
+  const GBL T* n_face;
+  const GBL double* detJ64;
   const GBL double* ghost;
   const GBL T* imp_q;
   const GBL T* imp_v;
@@ -170,12 +180,21 @@ __device__ __forceinline__ void copy_phys(const Phys<double>* src, Phys<T>* dst,
 
 template <typename T, typename S>
 __device__ __forceinline__ void fill_run(Run<T>& r, S& d) {
-  r.x_sp = (const GBL double*)d.x_sp;
-  r.detJ = (const GBL double*)d.detJ;
-  r.S_fp = (const GBL double*)d.S_fp;
-  r.Sj_sp = (const GBL double*)d.Sj_sp;
+  if constexpr (sizeof(T) == 8) {
+    r.x_sp = (const GBL T*)d.x_sp;
+    r.detJ = (const GBL T*)d.detJ;
+    r.S_fp = (const GBL T*)d.S_fp;
+    r.Sj_sp = (const GBL T*)d.Sj_sp;
+    r.n_face = (const GBL T*)d.n_face;
+  } else {
+    r.x_sp = (const GBL T*)d.x_sp_f;
+    r.detJ = (const GBL T*)d.detJ_f;
+    r.S_fp = (const GBL T*)d.S_fp_f;
+    r.Sj_sp = (const GBL T*)d.Sj_sp_f;
+    r.n_face = (const GBL T*)d.n_face_f;
+  }
+  r.detJ64 = (const GBL double*)d.detJ;
   r.nbr = (const GBL int32_t*)d.nbr;
-  r.n_face = (const GBL double*)d.n_face;
   r.ghost = (const GBL double*)d.ghost;
   r.imp_q = (const GBL T*)d.imp_q;
   r.imp_v = (const GBL T*)d.imp_v;
@@ -419,7 +438,7 @@ __device__ __forceinline__ T interp_rows(const T* sR, const T* w, int ws, int s0
 template <int N, typename T>
 __device__ __forceinline__ void load_normal(const Run<T>& R, int f, int ab, T n[3]) {
   constexpr int N2 = N * N;
-  const GBL double* nf = R.n_face + (R.e * 6 + f) * 3 * N2 + ab;
+  const GBL T* nf = R.n_face + (R.e * 6 + f) * 3 * N2 + ab;
   n[0] = (T)nf[0];
   n[1] = (T)nf[N2];
   n[2] = (T)nf[2 * N2];
@@ -729,7 +748,7 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
     copy_phys<T>(R.P, &sP, tid);
     const Phys<T>& P = sP;  // valid after the barrier that ends phase A
     const GBL double* Qe = R.Q + e * 9 * N3;
-    const GBL double* Se = R.S_fp + e * 9 * NF;
+    const GBL T* Se = R.S_fp + e * 9 * NF;
     const GBL int32_t* nb6 = R.nbr + e * 6;
     const bool use_kr = R.kr_on;
 
@@ -902,7 +921,7 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
         const int sp = tid;
         // FP64 quadrature weights in either arithmetic
         const DevTab<double>& td = tab<double>(N);
-        const double wq = td.W[ia0] * td.W[ia1] * td.W[ia2] * R.detJ[e * N3 + sp];
+        const double wq = td.W[ia0] * td.W[ia1] * td.W[ia2] * R.detJ64[e * N3 + sp];
         const GBL double* q = Qe + sp;
         const double rho = q[0];
         const double m2 = q[N3] * q[N3] + q[2 * N3] * q[2 * N3] + q[3 * N3] * q[3 * N3];
@@ -1341,6 +1360,12 @@ __global__ __launch_bounds__(256) void k_sph_profile(const double* Q, const doub
   }
 }
 
+// FP64 -> FP32 (round to nearest) copy of n values, grid-stride
+__global__ __launch_bounds__(256) void k_to_f32(const double* src, float* dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    dst[i] = (float)src[i];
+}
+
 // ---------------------------------------------------------------------------
 // diagnostics reduction (one block, fixed order)
 // ---------------------------------------------------------------------------
@@ -1477,6 +1502,10 @@ struct sdm_ctx {
   int arith = 0;
   bool bound = false;
   sdm_mesh mesh{};
+  // mixed arithmetic: FP32 copies of x_sp, detJ, S_fp, Sj_sp, n_face (one
+  // device allocation, made by sdm_mesh_bind, released by sdm_destroy)
+  float* geo32 = nullptr;
+  size_t geo32_off[5] = {0, 0, 0, 0, 0};
   int64_t n_group[4] = {0, 0, 0, 0};  // boundary faces per group
   // optional per-kernel timing: events recorded around every launch
   bool prof = false;
@@ -1535,6 +1564,13 @@ RunDesc make_desc(const sdm_ctx* c, const sdm_params* p, const double* Q, void* 
   r.Sj_sp = c->mesh.Sj_sp;
   r.nbr = c->mesh.nbr;
   r.n_face = c->mesh.n_face;
+  if (c->geo32) {
+    r.x_sp_f = c->geo32 + c->geo32_off[0];
+    r.detJ_f = c->geo32 + c->geo32_off[1];
+    r.S_fp_f = c->geo32 + c->geo32_off[2];
+    r.Sj_sp_f = c->geo32 + c->geo32_off[3];
+    r.n_face_f = c->geo32 + c->geo32_off[4];
+  }
   r.ghost = p ? p->ghost : nullptr;
   r.imp_q = p ? p->import_q : nullptr;
   r.imp_v = p ? p->import_v : nullptr;
@@ -1789,6 +1825,7 @@ sdm_status sdm_destroy(sdm_ctx* c) {
   if (c) {
     (void)hipSetDevice(c->device);
     for (hipEvent_t h : c->ev) (void)hipEventDestroy(h);
+    if (c->geo32) (void)hipFree(c->geo32);
   }
   delete c;
   return SDM_OK;
@@ -1842,6 +1879,31 @@ sdm_status sdm_mesh_bind(sdm_ctx* c, const sdm_mesh* m) {
       if (bf >= m->n_bfaces) return fail(SDM_EINVAL, "mesh_bind: boundary code out of range");
       ++ng[g];
     }
+  }
+  if (c->geo32) {
+    HIP_TRY(hipFree(c->geo32));
+    c->geo32 = nullptr;
+  }
+  c->bound = false;
+  if (c->arith == 1) {
+    // the FP32 kernels convert every geometry value to FP32 on use; they read
+    // these copies instead (the same values, half the bytes)
+    const int64_t E = m->n_elem, N = c->N, N2 = N * N, N3 = N2 * N, NF = (N + 1) * N2;
+    const int64_t cnt[5] = {E * 3 * N3, E * N3, E * 9 * NF, E * 9 * N3, E * 6 * 3 * N2};
+    const double* src[5] = {m->x_sp, m->detJ, m->S_fp, m->Sj_sp, m->n_face};
+    size_t total = 0;
+    for (int k = 0; k < 5; ++k) {
+      c->geo32_off[k] = total;
+      total += (size_t)((cnt[k] + 63) & ~int64_t(63));  // 256-byte aligned pieces
+    }
+    HIP_TRY(hipMalloc((void**)&c->geo32, total * sizeof(float)));
+    for (int k = 0; k < 5; ++k) {
+      const int64_t blocks = std::min<int64_t>((cnt[k] + 255) / 256, 65536);
+      hipLaunchKernelGGL(k_to_f32, dim3((unsigned)blocks), dim3(256), 0, nullptr, src[k], c->geo32 + c->geo32_off[k],
+                         cnt[k]);
+      HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(nullptr));
   }
   c->mesh = *m;
   for (int g = 0; g < 4; ++g) c->n_group[g] = ng[g];
