@@ -845,15 +845,24 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
       const int st = d == 0 ? 1 : (d == 1 ? N : N2);
       const int s0 = sp_line<N>(d, ab % N, ab / N, 0);
       const T* wI = sI + ((f & 1) ? N : 0) * N * is;
-      T own[9];
+      // the rows are read two ahead of their use (as in phase C)
+      T own[9], wv[N], rv[3][9];
 #pragma unroll
-      for (int v = 0; v < 9; ++v) own[v] = wI[0] * sR[s0 * RS + v];
+      for (int i = 0; i < N; ++i) wv[i] = wI[i * is];
 #pragma unroll
-      for (int i = 1; i < N; ++i) {
-        const T wi = wI[i * is];
-        const T* row = sR + (s0 + i * st) * RS;
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int v = 0; v < 9; ++v) own[v] += wi * row[v];
+        for (int v = 0; v < 9; ++v) rv[i][v] = sR[(s0 + i * st) * RS + v];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        if (i + 2 < N) {
+#pragma unroll
+          for (int v = 0; v < 9; ++v) rv[(i + 2) % 3][v] = sR[(s0 + (i + 2) * st) * RS + v];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int v = 0; v < 9; ++v) own[v] = i == 0 ? wv[0] * rv[0][v] : own[v] + wv[i] * rv[i % 3][v];
+        __builtin_amdgcn_sched_barrier(0);
       }
       T* dst = sU + (f * N2 + ab) * 9;
       const int g = code >= 0 ? -1 : ((-code - 1) & 3);
@@ -893,16 +902,36 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
         const T* row0 = sR + (tid - i * st) * RS;
         const T* j0 = sU + ((2 * d) * N2 + pq) * 9;
         const T* jN = sU + ((2 * d + 1) * N2 + pq) * 9;
+        // the LDS reads run two rows ahead of their use (scheduling
+        // barriers keep the compiler from regrouping them, which would leave
+        // only a few reads in flight and a wait for each group in turn)
         const T c0 = sD[(i * NP) * ds], cN = sD[(i * NP + N) * ds];
+        T a0[9], aN[9], w[N], rv[3][9];
+#pragma unroll
+        for (int v = 0; v < 9; ++v) {
+          a0[v] = j0[v];
+          aN[v] = jN[v];
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) w[j] = sDI[(i * N + j) * dis];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int v = 0; v < 9; ++v) rv[j][v] = row0[j * st * RS + v];
+        __builtin_amdgcn_sched_barrier(0);
         T dq[9];
 #pragma unroll
-        for (int v = 0; v < 9; ++v) dq[v] = c0 * j0[v] + cN * jN[v];
+        for (int v = 0; v < 9; ++v) dq[v] = c0 * a0[v] + cN * aN[v];
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-          const T w = sDI[(i * N + j) * dis];
-          const T* row = row0 + j * st * RS;
+          if (j + 2 < N) {
 #pragma unroll
-          for (int v = 0; v < 9; ++v) dq[v] += w * row[v];
+            for (int v = 0; v < 9; ++v) rv[(j + 2) % 3][v] = row0[(j + 2) * st * RS + v];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int v = 0; v < 9; ++v) dq[v] += w[j] * rv[j % 3][v];
+          __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int v = 0; v < 9; ++v)
