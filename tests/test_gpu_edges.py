@@ -96,3 +96,34 @@ def test_batch_rejects_empty_and_mismatched(sd):
     assert sd._lib.sdm_batch_workspace_size(0, C.byref(nb)) != sd.SDM_OK
     items = (sd.BatchItem * 1)()
     assert sd._lib.sdm_batch_stage(items, 0, None, 0, 0, None) != sd.SDM_OK
+
+
+def test_mixed_geometry_copy_follows_rebind(sd):
+    """FP32-mixed reads the FP32 geometry copies sdm_mesh_bind makes: a
+    rebind of the same arrays gives bitwise the same residual; arrays
+    changed in place are not seen until the next bind, after which the
+    residual equals a fresh context's on the new geometry."""
+    import torch
+    print("mixed geometry rebind", flush=True)
+    ma, mb = sd.shell(2, 1, 3, 0.70, 0.98), sd.shell(2, 1, 3, 0.60, 0.95)
+    bg = inp.Background(3.0)
+    Q = torch.from_numpy(inp.shell_state(ma.x_sp, bg, 4)).cuda()
+    prm = sd.make_params(**inp.run_params(4, bg), c_h=1.0)
+    s = sd.Solver(ma, arith=1)
+
+    def rebind():
+        md = sd.MeshDesc(ma.E, ma.NB, s.x_sp.data_ptr(), s.detJ.data_ptr(), s.S_fp.data_ptr(),
+                         s.Sj_sp.data_ptr(), s.nbr.data_ptr(), s.n_face.data_ptr())
+        sd._check(sd._lib.sdm_mesh_bind(s._h, C.byref(md)))
+
+    r1 = s.residual(prm, Q).clone()
+    rebind()
+    assert torch.equal(s.residual(prm, Q), r1)
+    for k in ("x_sp", "detJ", "S_fp", "Sj_sp", "n_face"):
+        getattr(s, k).copy_(torch.from_numpy(np.ascontiguousarray(getattr(mb, k))))
+    assert torch.equal(s.residual(prm, Q), r1)  # the copies made at the last bind
+    rebind()
+    r2 = s.residual(prm, Q)
+    ref = sd.Solver(mb, arith=1).residual(prm, Q)
+    assert not torch.equal(r2, r1)
+    assert torch.equal(r2, ref)
