@@ -150,8 +150,9 @@ sdm_status sdm_destroy(sdm_ctx* ctx);
  * x_sp, detJ, S_fp, Sj_sp and n_face, 22.9 KB per element at p = 5, which the
  * FP32 residual kernels read instead (the values they would round on use, at
  * half the bytes); the context owns them until sdm_destroy or the next bind,
- * so rebind after changing those arrays.  Synchronous; SDM_EHIP if the
- * allocation fails. */
+ * so rebind after changing those arrays.  Synchronous, on the null stream
+ * (writes to the arrays on other non-blocking streams must be complete
+ * first); SDM_EHIP if the allocation fails. */
 typedef struct {
   int64_t n_elem;
   int64_t n_bfaces;
