@@ -409,7 +409,8 @@ sdm_status sdm_batch_workspace_size(int n_items, size_t* bytes);
  * others on library-owned streams (default priority, created once per
  * device) that start after the work-list copy and that `stream` waits for:
  * the groups overlap on the device, and work enqueued on `stream`
- * afterwards sees every run's stage done.  Every run gets exactly the
+ * afterwards sees every run's stage done (calls from several host threads
+ * take turns enqueueing on those streams).  Every run gets exactly the
  * arithmetic of sdm_rk_stage on its own: results are bitwise identical
  * alone and in any batch.  batch_ws must not be reused by another call
  * before this one's work on `stream` has been enqueued (the next call on

@@ -1748,6 +1748,10 @@ struct BatchStreams {
 };
 std::mutex g_bs_mu;
 BatchStreams g_bs[64];
+// held while one call enqueues on a device's library streams and records
+// their fork and join events, so that calls from several host threads do
+// not interleave their records and waits
+std::mutex g_bs_enqueue[64];
 
 sdm_status batch_streams(int device, int n_side, BatchStreams** out) {
   std::lock_guard<std::mutex> lk(g_bs_mu);
@@ -2234,8 +2238,10 @@ sdm_status sdm_batch_stage(const sdm_batch_item* items, int n_items, void* batch
   // library streams that wait for the table copy; the caller's stream then
   // waits for them, so work of different degrees overlaps on the device
   BatchStreams* bs = nullptr;
+  std::unique_lock<std::mutex> enqueue;
   if (G > 1) {
     if ((st = batch_streams(c0->device, G - 1, &bs)) != SDM_OK) return st;
+    enqueue = std::unique_lock<std::mutex>(g_bs_enqueue[c0->device]);
     HIP_TRY(hipEventRecord(bs->fork, s));
   }
   char* base = (char*)batch_ws;

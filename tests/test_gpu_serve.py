@@ -223,3 +223,66 @@ def test_batched_stages_match_oracle(srv, oracle):
         got = s.state.cpu().numpy()
         err = np.abs(got - qo).max(axis=(0, 2)) / (np.abs(qo).max(axis=(0, 2)) + dt * scale)
         assert (err <= 1e-12).all(), err
+
+
+def test_batches_from_two_host_threads(srv):
+    """Two host threads each advance their own mixed-degree batch on their
+    own stream at the same time (the library's streams and events for the
+    extra degree groups are shared per device): every run is bitwise what
+    the same calls give one after the other."""
+    import ctypes as C
+    import threading
+
+    import torch
+
+    from paper_2502_17805_amd import sdmhd as sd
+    groups = (((2, 1, 3, 3.0, 21), (2, 1, 5, 5.0, 22)), ((2, 2, 3, 5.0, 23), (2, 1, 5, 3.0, 24)))
+
+    def make(specs):
+        solvers, prms, dts = [], [], []
+        for Nz, Nr, p, N_rho, seed in specs:
+            m = sd.shell(Nz, Nr, p)
+            bg = inp.Background(N_rho)
+            Q = inp.shell_state(m.x_sp, bg, seed)
+            pr = inp.run_params(seed, bg)
+            ch = inp.glm_speed(Q)
+            pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
+            s = sd.Solver(m)
+            s.set_state(Q)
+            solvers.append(s)
+            prms.append(sd.make_params(**pr))
+            dts.append(inp.time_step(Q, m.Sj_sp, ch, 0.1))
+        nb = C.c_size_t()
+        sd._check(sd._lib.sdm_batch_workspace_size(len(solvers), C.byref(nb)))
+        bws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+        return solvers, prms, min(dts), bws, int(nb.value)
+
+    def advance(run, stream, errors):
+        solvers, prms, dt, bws, nb = run
+        try:
+            with torch.cuda.stream(stream):
+                for _ in range(3):
+                    _batch_step(sd, solvers, prms, dt, bws, nb, C.c_void_p(stream.cuda_stream))
+            stream.synchronize()
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    print("two host threads, mixed-degree batches", flush=True)
+    runs = [make(g) for g in groups]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in groups]
+    errors = []
+    threads = [threading.Thread(target=advance, args=(r, st, errors)) for r, st in zip(runs, streams)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for g, run in zip(groups, runs):
+        ref = make(g)
+        torch.cuda.synchronize()
+        advance(ref, streams[0], errors)
+        assert not errors, errors
+        for a, b, spec in zip(run[0], ref[0], g):
+            assert torch.isfinite(b.state).all()
+            assert torch.equal(a.state, b.state), spec
