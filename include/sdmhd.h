@@ -10,9 +10,10 @@
  * named there.  Device work is hand-written HIP; every pointer marked
  * "device" must be device memory of the context's GPU, allocated and owned
  * by the caller (the library never frees it and allocates no device memory
- * except its static constant tables and the static trace scratch of
- * sdm_ssprk53_step_noalloc).  Calls that take a stream only enqueue work on
- * it; results are valid after the stream is synchronised.
+ * except its static constant tables, the static trace scratch of
+ * sdm_ssprk53_step_noalloc and, for a mixed-arithmetic context, the FP32
+ * geometry copies sdm_mesh_bind makes).  Calls that take a stream only
+ * enqueue work on it; results are valid after the stream is synchronised.
  *
  * Layouts (all row-major, last index fastest):
  *   N      = p + 1 solution points per direction; N3 = N^3; NF = (N+1) N^2
@@ -275,8 +276,8 @@ sdm_status sdm_ssprk53_step(sdm_ctx* ctx, const sdm_params* prm, double* const* 
  * x 4 in FP32-mixed (2,427 elements at p = 5 in FP64, 4,854 in
  * FP32-mixed); a larger mesh returns SDM_EINVAL with the limit in the
  * message.  The first stage always recomputes the traces of regs[0] (no
- * traces_valid).  Calls, no-allocation or not, allocate nothing, and this
- * one frees nothing.  All contexts on one device share the one array:
+ * traces_valid).  Stage and step calls, no-allocation or not, allocate
+ * nothing, and this one frees nothing.  All contexts on one device share the one array:
  * calls that may overlap on one device (different streams, or other
  * threads) race and must be serialised by the caller; a call on one stream
  * after another completes is safe. */
