@@ -105,11 +105,17 @@ class _MeshCache:
 def request_bytes(q: Request) -> int:
     """Device bytes a request holds while resident: four FP64 state
     registers, the workspace (face traces, viscous traces, partial residual
-    in the arithmetic type), and its mesh arrays (counted per request)."""
+    in the arithmetic type), its mesh arrays (counted per request) and, in
+    the mixed arithmetic, the FP32 geometry copies its context makes."""
     E, N = 6 * q.Nz * q.Nz * q.Nr, q.p + 1
     rs = 4 if q.arith else 8
     ws = rs * E * (6 * 9 * N * N + 6 * 7 * N * N + 9 * N ** 3) + 3 * 256
-    return 4 * 8 * 9 * q.dof + ws + _MeshCache.device_bytes(q.Nz, q.Nr, q.p)
+    mesh = _MeshCache.device_bytes(q.Nz, q.Nr, q.p)
+    geo32 = 0
+    if q.arith:
+        N3, NF = N ** 3, (N + 1) * N * N
+        geo32 = 4 * E * (3 * N3 + N3 + 9 * NF + 9 * N3 + 18 * N * N) + 5 * 256
+    return 4 * 8 * 9 * q.dof + ws + mesh + geo32
 
 
 def prepare(req: Request, mesh):
