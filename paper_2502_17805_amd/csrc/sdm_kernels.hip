@@ -262,6 +262,14 @@ template <int N>
 constexpr int block_threads() {
   return ((N * N * N + 63) / 64) * 64 < 64 ? 64 : ((N * N * N + 63) / 64) * 64;
 }
+// k_finish: at least one lane per face point, so that the neighbours'
+// viscous fluxes travel with the element's own loads (p = 3: 128 lanes for
+// 96 face points, k_finish 0.224 -> 0.199 ms FP64, 0.158 -> 0.134 ms
+// FP32-mixed on 55,296 elements; the volume pass keeps one lane per SP)
+template <int N>
+constexpr int finish_threads() {
+  return block_threads<N>() >= 6 * N * N ? block_threads<N>() : ((6 * N * N + 63) / 64) * 64;
+}
 
 // Face point (face, ab) handled by lane t of k_volume's face passes, which
 // read the N point rows of the line through each face point.  For N = 6 the
@@ -1218,7 +1226,7 @@ struct FinLds {
 
 template <int N, typename T, bool STAGE>
 __device__ __forceinline__ void finish_body(const Run<T>& R, int tid, char* lds) {
-  constexpr int N2 = N * N, N3 = N2 * N, NP = N + 1, BS = block_threads<N>();
+  constexpr int N2 = N * N, N3 = N2 * N, NP = N + 1, BS = finish_threads<N>();
   static_assert(BS >= N3, "one solution point per thread");
   using Ly = FinLds<N, T, STAGE>;
   T* const sV = reinterpret_cast<T*>(lds + Ly::oV);
@@ -1317,7 +1325,7 @@ __device__ __forceinline__ void finish_body(const Run<T>& R, int tid, char* lds)
 }
 
 template <int N, typename T, bool STAGE>
-__global__ __launch_bounds__(block_threads<N>()) void k_finish(Launch L) {
+__global__ __launch_bounds__(finish_threads<N>()) void k_finish(Launch L) {
   __shared__ __align__(16) char lds[FinLds<N, T, STAGE>::bytes];
   // one element per workgroup; no loop, so nothing per element is kept
   // live across elements
@@ -1624,8 +1632,8 @@ hipError_t launch_all(int which, const Launch& L, hipStream_t s, int64_t cap) {
       case 0: hipLaunchKernelGGL((k_traces<N, T>), dim3(grid), dim3(BS), 0, s, Lc); break;
       case 1: hipLaunchKernelGGL((k_volume<N, T, false>), dim3(grid), dim3(BS), 0, s, Lc); break;
       case 2: hipLaunchKernelGGL((k_volume<N, T, true>), dim3(grid), dim3(BS), 0, s, Lc); break;
-      case 3: hipLaunchKernelGGL((k_finish<N, T, false>), dim3(grid), dim3(BS), 0, s, Lc); break;
-      case 4: hipLaunchKernelGGL((k_finish<N, T, true>), dim3(grid), dim3(BS), 0, s, Lc); break;
+      case 3: hipLaunchKernelGGL((k_finish<N, T, false>), dim3(grid), dim3(finish_threads<N>()), 0, s, Lc); break;
+      case 4: hipLaunchKernelGGL((k_finish<N, T, true>), dim3(grid), dim3(finish_threads<N>()), 0, s, Lc); break;
       default: return hipErrorInvalidValue;
     }
     const hipError_t e = hipGetLastError();
