@@ -45,11 +45,24 @@
  *                       toroidal / radial / dipole fields, constant radial,
  *                       polar and azimuthal flows, bin volumes = shell
  *                       volumes of the bins
- * Parity unpinned beyond invariants: the wall treatments (mirror and common
- * states, stress-free and magnetic wall fluxes) are pinned only by zero
- * mass flux, zero tangential stress, zero energy flux through a conducting
- * adiabatic wall and the prescribed heat input; their remaining details
- * follow the stated readings of the boundary conditions.
+ *   wall treatments     (tests/test_oracle_walls.py) the exact equilibria
+ *                       of each wall kind: a uniform field normal to
+ *                       radial-field walls and tangential to conducting
+ *                       ones, a uniform flow along impenetrable stress-free
+ *                       walls, a uniform cleaning field at conducting walls,
+ *                       a gas at the wall temperature at fixed-temperature
+ *                       walls (zero residual; the other kind of wall or the
+ *                       violated condition gives none); hotter / colder
+ *                       walls heat / cool their own layer; the reflection
+ *                       force of a flow into a wall, the cleaning field's
+ *                       wall fluxes, the heat flux through a fixed-
+ *                       temperature wall and the normal traction at a
+ *                       stress-free wall in closed form; no resistive flux
+ *                       through a conducting wall, -eta J_t x n through a
+ *                       radial-field one; each with a planted mistake it
+ *                       catches.  Also zero mass flux, zero tangential
+ *                       stress, zero energy flux through a conducting
+ *                       adiabatic wall and the prescribed heat input.
  */
 #ifndef SDMHD_ORACLE_H
 #define SDMHD_ORACLE_H
