@@ -105,6 +105,22 @@ def test_residual_dirichlet_warped_box_and_single_element(sd, oracle):
         _check_residual(sd, oracle, ml, mo, Q, pr, ghost=gh)
 
 
+@pytest.mark.parametrize("p", [3, 5])
+def test_residual_every_wall_kind_box(sd, oracle, p):
+    """Flat physical walls at z = 0 (group 0) and z = Lz (group 1) of a box
+    periodic in x and y, a smooth random state: every magnetic wall kind and
+    every thermal wall kind at each of the two walls."""
+    ml = sd.box(3, 3, 2, p, L=(1.0, 0.9, 0.7), periodic=3)
+    mo = oracle.Mesh.box(p + 1, 3, 3, 2, L=(1.0, 0.9, 0.7), periodic=3)
+    Q = inp.smooth_random_state(mo.get("x_sp"), 8)
+    for mag, th in (((0, 1), (0, 1)), ((1, 0), (1, 0)), ((0, 1), (1, 0)), ((1, 0), (0, 1))):
+        print(f"walls p={p} mag={mag} th={th}", flush=True)
+        pr = dict(nu=1e-2, kappa=2e-2, eta=1.5e-2, c_h=1.5, glm_a=0.3, powell=1, wall_kind=(0, 0),
+                  wall_mag=mag, wall_th=th, q_wall=(0.03, -0.02), T_wall=(1.1, 0.8),
+                  kr_scale=0.01, kr_c0=1.0)
+        _check_residual(sd, oracle, ml, mo, Q, pr)
+
+
 def test_ssprk53_steps_c1(sd, oracle):
     """The C1 run: 10 SSPRK(5,3) steps on the 48-element shell; every step's
     state against the oracle's."""
