@@ -660,16 +660,19 @@ __device__ __forceinline__ void volume_epilogue(const Run<T>& R, const Phys<T>& 
 // k_volume
 // ---------------------------------------------------------------------------
 // waves per SIMD the volume pass is compiled for (its register budget is
-// 512 / waves): FP64 two (LDS also admits two workgroups per CU), FP32 four
+// 512 / waves): FP64 two (LDS also admits two workgroups per CU), FP32 four,
+// except N = 4, 5 and 7, whose FP32 passes need more than 128 registers
+// (N = 7: and LDS admits fewer workgroups) and get three
 #ifndef SDM_VOLUME_WAVES_F64
 #define SDM_VOLUME_WAVES_F64 2
 #endif
 #ifndef SDM_VOLUME_WAVES_F32
 #define SDM_VOLUME_WAVES_F32 4
 #endif
-template <typename T>
+template <int N, typename T>
 constexpr int volume_waves() {
-  return sizeof(T) == 8 ? SDM_VOLUME_WAVES_F64 : SDM_VOLUME_WAVES_F32;
+  return sizeof(T) == 8 ? SDM_VOLUME_WAVES_F64
+                        : ((N == 4 || N == 5 || N == 7) && SDM_VOLUME_WAVES_F32 > 3 ? 3 : SDM_VOLUME_WAVES_F32);
 }
 
 // Interior flux points of one family on FP64 MFMA (v_mfma_f64_4x4x4f64, four
@@ -1173,7 +1176,7 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
 }
 
 template <int N, typename T, bool DIAG>
-__global__ __launch_bounds__(block_threads<N>()) __attribute__((amdgpu_waves_per_eu(volume_waves<T>())))
+__global__ __launch_bounds__(block_threads<N>()) __attribute__((amdgpu_waves_per_eu(volume_waves<N, T>())))
 void k_volume(Launch L) {
   __shared__ __align__(16) char lds[VolLds<N, T>::bytes];
   // one element per workgroup; no loop, so nothing per element is kept
