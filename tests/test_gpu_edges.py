@@ -70,6 +70,9 @@ def test_mesh_bind_rejects_empty_and_corrupt_tables(sd):
             return sd.MeshDesc(E, NB, dev["x_sp"].data_ptr(), dev["detJ"].data_ptr(), dev["S_fp"].data_ptr(),
                                dev["Sj_sp"].data_ptr(), nbr.data_ptr(), dev["n_face"].data_ptr())
         assert sd._lib.sdm_mesh_bind(h, C.byref(desc(0, 0, dev["nbr"]))) != sd.SDM_OK
+        # past the largest mesh the element index fields can address (checked
+        # before the table is read)
+        assert sd._lib.sdm_mesh_bind(h, C.byref(desc(1 << 25, m.NB, dev["nbr"]))) != sd.SDM_OK
         for bad in (m.E << 6, -(1 + 3 + 4 * m.NB), -(1 + 4 * m.NB)):  # element, import face, wall face
             nb = dev["nbr"].clone()
             nb[0, 0] = int(bad)
