@@ -1,7 +1,7 @@
 """GPU edge cases: every supported degree (p = 1 .. 6; p = 6 is the largest
-whose FP64 workgroup fits in LDS), and the error paths of the C ABI that
-guard a launch (every bad argument is rejected on the host before any
-kernel runs)."""
+whose FP64 workgroup fits in LDS) in both arithmetics, and the error paths
+of the C ABI that guard a launch (every bad argument is rejected on the
+host before any kernel runs)."""
 import ctypes as C
 
 import numpy as np
@@ -44,6 +44,15 @@ def test_every_degree_residual_and_step(sd, oracle, p):
     qo = mo.step(po, Q, dt)
     err = np.abs(s.state.cpu().numpy() - qo).max(axis=(0, 2))
     assert (err <= TOL * (np.abs(qo).max(axis=(0, 2)) + dt * ts)).all()
+    # FP32-mixed at this degree: the residual within the mixed bound (1e-5 of
+    # the term scale) and the step's FP64 accumulation around it
+    m32 = sd.Solver(ml, arith=1)
+    R32 = m32.residual(pg, torch.from_numpy(Q).cuda()).cpu().numpy()
+    assert (np.abs(R32 - Ro).max(axis=(0, 2)) <= 1e-5 * ts).all()
+    m32.set_state(Q)
+    m32.step(pg, dt)
+    err = np.abs(m32.state.cpu().numpy() - qo).max(axis=(0, 2))
+    assert (err <= 1e-5 * (np.abs(qo).max(axis=(0, 2)) + dt * ts)).all()
 
 
 def _ctx(sd, p=3, arith=0):
