@@ -185,11 +185,13 @@ def test_nan_run_is_evicted(srv):
         assert np.array_equal(alone[0].state, res[q.rid].state), q.rid
 
 
-def test_batched_stages_match_oracle(srv, oracle):
+@pytest.mark.parametrize("arith,tol", [(0, 1e-12), (1, 1e-5)])
+def test_batched_stages_match_oracle(srv, oracle, arith, tol):
     """Three runs of different degrees, shell sizes and backgrounds advanced
     together by sdm_batch_stage: each run's state after two SSPRK(5,3) steps
-    against the FP64 oracle's, within 1e-12 of max|u_v| + dt T_v.  The inputs
-    are made from the oracle's meshes."""
+    against the FP64 oracle's, within 1e-12 (FP64) or the mixed bound 1e-5
+    (FP32-mixed) of max|u_v| + dt T_v.  The inputs are made from the
+    oracle's meshes."""
     import ctypes as C
 
     import torch
@@ -203,7 +205,7 @@ def test_batched_stages_match_oracle(srv, oracle):
         pr = inp.run_params(seed, bg)
         ch = inp.glm_speed(Q)
         pr.update(c_h=ch, glm_a=ch / (bg.rt - bg.rb))
-        s = sd.Solver(sd.shell(Nz, Nr, p))
+        s = sd.Solver(sd.shell(Nz, Nr, p), arith=arith)
         s.set_state(torch.from_numpy(Q))
         runs.append((s, sd.make_params(**pr), oracle.make_params(**pr), mo, Q))
     dt = 2e-3
@@ -222,7 +224,7 @@ def test_batched_stages_match_oracle(srv, oracle):
             qo = mo.step(po, qo, dt)
         got = s.state.cpu().numpy()
         err = np.abs(got - qo).max(axis=(0, 2)) / (np.abs(qo).max(axis=(0, 2)) + dt * scale)
-        assert (err <= 1e-12).all(), err
+        assert (err <= tol).all(), err
 
 
 def test_batches_from_two_host_threads(srv):
