@@ -614,7 +614,7 @@ __device__ __forceinline__ void volume_epilogue(const Run<T>& R, const Phys<T>& 
     T gv[3] = {T(0), T(0), T(0)};
     if (P.GM != T(0)) {
       const T r2 = xs[0] * xs[0] + xs[1] * xs[1] + xs[2] * xs[2];
-      const T sc = -P.GM / (r2 * sqrt(r2));
+      const T sc = -P.GM * recip(r2 * sqrt_fast(r2));
       gv[0] = sc * xs[0]; gv[1] = sc * xs[1]; gv[2] = sc * xs[2];
     }
     const T ir = recip(q[0]);
@@ -884,7 +884,7 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
         T qo[9], qc[9];
 #pragma unroll
         for (int v = 0; v < 9; ++v) qo[v] = own[v];
-        const T inn = recip(sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]));
+        const T inn = recip(sqrt_fast(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]));
         const T nh[3] = {n[0] * inn, n[1] * inn, n[2] * inn};
         wall_common(qo, nh, g, P, qc);
 #pragma unroll
@@ -1064,7 +1064,7 @@ __device__ __forceinline__ void volume_body(const Run<T>& R, int tid, char* lds)
         for (int c = 0; c < 7; ++c) F[1 + c] -= T(0.5) * Fv[c];
       } else {
         // physical wall
-        const T nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        const T nn = sqrt_fast(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
         const T inn = recip(nn);
         const T nh[3] = {n[0] * inn, n[1] * inn, n[2] * inn};
         wall_mirror(qf, nh, g, P, qx);

@@ -36,6 +36,23 @@ __device__ __forceinline__ double recip(double x) {
 }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// sqrt(x) for x >= 0 (FP64: the hardware reciprocal square root y, one
+// coupled Newton step on g = x y and h = y / 2, then one correction of g
+// by h (x - g^2): within an ulp of the rounded root, against the two
+// corrections and the range scaling of the IEEE sequence.  Arguments below
+// 1e-290, where the scaling would matter, give 0; negative arguments and NaN
+// give NaN.  FP32: the hardware square root, within 1 ulp.)
+__device__ __forceinline__ double sqrt_fast(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  g = fma(fma(-g, g, x), h, g);
+  return x >= 1e-290 ? g : (x >= 0.0 ? 0.0 : g);
+}
+__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // value of a two-wall parameter for wall group g (a select, so the
 // parameter block stays in registers)
 template <typename X>
@@ -246,7 +263,7 @@ __device__ __forceinline__ T fast_speed(const T* q, const T nh[3], const Phys<T>
   const T s = a2 + b2;
   T disc = s * s - T(4) * a2 * Bn * Bn * ir;
   disc = disc > T(0) ? disc : T(0);
-  return sqrt(T(0.5) * (s + sqrt(disc)));
+  return sqrt_fast(T(0.5) * (s + sqrt_fast(disc)));
 }
 
 // Rusanov flux from `own` to `oth` through the unnormalised normal n pointing
@@ -255,7 +272,7 @@ __device__ __forceinline__ T fast_speed(const T* q, const T nh[3], const Phys<T>
 template <typename T>
 __device__ __forceinline__ void rusanov(const T* own, const T* oth, const T n[3], const Phys<T>& P,
                                         T F[9]) {
-  const T nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  const T nn = sqrt_fast(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
   const T inn = recip(nn);
   const T nh[3] = {n[0] * inn, n[1] * inn, n[2] * inn};
   const T s1 = fabs((own[1] * nh[0] + own[2] * nh[1] + own[3] * nh[2]) * recip(own[0])) + fast_speed(own, nh, P);
@@ -346,7 +363,7 @@ __device__ __forceinline__ void wall_viscous_sub(const ViscLocal<T>& v, const T 
 
 template <typename T>
 __device__ __forceinline__ T kappa_r(const T x[3], const Phys<T>& P) {
-  const T w = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) * P.kr_w;
+  const T w = sqrt_fast(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) * P.kr_w;
   return P.kr_scale * (P.kr_c0 + P.kr_c1 * w + P.kr_c2 * w * w);
 }
 
